@@ -1,0 +1,197 @@
+/*
+ * tdmps -- MPS time evolution of the ab-initio electronic Hamiltonian on one MI355X.
+ *
+ * C ABI of the library.  It follows the method of Frahm & Pfannkuche,
+ * "Ultrafast ab-initio Quantum Chemistry Using Matrix Product States" (arXiv:1902.08489):
+ * the time-dependent Schroedinger equation on the Fock space (Methods, Eqs. (sg) and
+ * (time_evo_opera)) with the Hamiltonian of Eq. (hamil), states stored as matrix
+ * product states (Eq. (mps)), and the three MPS operations of the "Operations on MPS"
+ * section -- scaling, addition and application of the Hamiltonian, both done by the
+ * variational fit of Eq. (add_min) -- composed into RK4 (Eqs. (k1-k4), (rk_add)) and
+ * Krylov (Eqs. (kry_non), (kry_orth), (krylov_evo)) time steps.
+ *
+ * Conventions
+ *  - Atomic units (hbar = 1).  L spatial orbitals; orbital p holds the local state
+ *    n = n_up + 2 n_dn: |0>, |up>, |dn>, |up dn> = a+_{p up} a+_{p dn} |0>.  Spin orbitals
+ *    are ordered 1up, 1dn, 2up, 2dn, ...; a determinant |n_1 ... n_L> is the product of
+ *    creators in that order (lowest leftmost) acting on the vacuum.
+ *  - Dense state vectors have 4^L complex entries indexed by sum_p n_p 4^(L-1-p)
+ *    (orbital 1 most significant).  Complex numbers are interleaved (re, im) doubles.
+ *  - States are block sparse by the charge (N_up, N_dn) of the orbitals left of each
+ *    bond (U(1) x U(1)).  A site tensor A_i[a, n, b] is stored, for each left sector in
+ *    bond order, as a row-major panel of D_a rows whose columns are the blocks
+ *    n = 0..3 (those whose right sector exists), each D_b wide.
+ *  - Ownership: every `out` handle is new, owned by the caller and released with the
+ *    matching *_destroy.  Host arrays passed in are copied and never retained.  Input
+ *    handles are never modified except by the explicitly in-place calls.
+ *  - Errors: a negative status is returned, `*out` is left NULL and tdmps_last_error()
+ *    (thread local) describes the failure.  No C++ exception crosses this boundary.
+ *  - Streams: all device work of a context is ordered on its stream.  Calls that return
+ *    host scalars or host arrays synchronise that stream before returning.
+ *  - Precision: contractions run in the precision of tdmps_fit_params.precision; the
+ *    SVD truncation, the Krylov matrices and their exponential are always FP64.
+ */
+#ifndef TDMPS_H
+#define TDMPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tdmps_ctx_s* tdmps_ctx;
+typedef struct tdmps_mpo_s* tdmps_mpo;
+typedef struct tdmps_mps_s* tdmps_mps;
+typedef struct tdmps_heff_s* tdmps_heff;
+typedef int32_t tdmps_status;
+
+enum {
+  TDMPS_OK = 0,
+  TDMPS_ERR_ARG = -1,         /* bad argument (size, NULL, occupation code, L)          */
+  TDMPS_ERR_SECTOR = -2,      /* charge sectors of the operands do not match            */
+  TDMPS_ERR_OOM = -3,         /* device or host allocation failed                       */
+  TDMPS_ERR_HIP = -4,         /* a HIP runtime call failed                              */
+  TDMPS_ERR_NUMERIC = -5,     /* NaN/Inf in inputs, or an SVD that did not converge      */
+  TDMPS_ERR_SINGULAR = -6,    /* Krylov overlap matrix not positive definite            */
+  TDMPS_ERR_UNSUPPORTED = -7  /* feature not available in this build                    */
+};
+
+enum { TDMPS_FP64 = 0, TDMPS_FP32 = 1, TDMPS_BF16X3 = 2 };
+enum { TDMPS_KRYLOV_ORTHO = 0, TDMPS_KRYLOV_NONORTHO = 1 };
+
+/* Parameters of the variational fit (Methods, Eq. (add_min)).
+ *  Dmax       : maximal bond dimension D kept after every two-site update.
+ *  n_sweeps   : maximal number of sweeps; a sweep is a left-to-right pass over the bonds
+ *               followed by a right-to-left pass (the paper reports about ten).
+ *  conv_tol   : stop when the relative change of |C|^2 between sweeps is below this
+ *               (0 = always run n_sweeps).
+ *  svd_cutoff : singular values <= svd_cutoff * sigma_max are dropped (at least one kept).
+ *  precision  : TDMPS_FP64 / TDMPS_FP32 / TDMPS_BF16X3 for the block contractions.
+ *  batched    : 1 = one grouped launch per contraction stage (default); 0 = one launch
+ *               per block product (reference form used for comparisons). */
+typedef struct {
+  int32_t Dmax;
+  int32_t n_sweeps;
+  double conv_tol;
+  double svd_cutoff;
+  int32_t precision;
+  int32_t batched;
+} tdmps_fit_params;
+
+typedef struct {
+  int32_t sweeps_used;
+  int32_t max_bond;
+  double discarded_max; /* largest discarded weight of one two-site update */
+  double discarded_sum; /* sum over the updates of the last sweep          */
+  double norm2;         /* |C|^2 of the result                             */
+} tdmps_fit_info;
+
+const char* tdmps_last_error(void);
+
+/* Context: one GPU, one stream.  hip_stream may be NULL (the library creates and owns a
+ * stream) or a borrowed hipStream_t that must outlive the context. */
+tdmps_status tdmps_ctx_create(int32_t device, void* hip_stream, tdmps_ctx* out);
+tdmps_status tdmps_ctx_destroy(tdmps_ctx ctx);
+/* Counters of the last operation: out[0] = algorithmic flops of the H_eff contractions,
+ * out[1] = their kernel time in ms, out[2] = env-update flops, out[3] = env time ms,
+ * out[4] = SVD time ms, out[5] = number of two-site updates. */
+tdmps_status tdmps_ctx_counters(tdmps_ctx ctx, double* out8);
+tdmps_status tdmps_ctx_reset_counters(tdmps_ctx ctx);
+
+/* ---------------------------------------------------------------- Hamiltonian MPO
+ * Exact MPO of Eq. (hamil): H = sum_pq h_pq a+_{p s} a_{q s}
+ *   + 1/2 sum_pqrs (pr|qs) a+_{p s} a+_{q t} a_{s t} a_{r s} + e0,
+ * i.e. V_ijkl = (ik|jl) from chemists' integrals.  h: L*L row-major symmetric; eri: L^4
+ * row-major (pq|rs) with 8-fold symmetry.  Returns TDMPS_ERR_NUMERIC for NaN/Inf input.
+ * ctx may be NULL for a host-only operator (tdmps_mpo_to_dense, tdmps_mpo_det_element). */
+tdmps_status tdmps_mpo_from_integrals(tdmps_ctx ctx, int32_t L, const double* h, const double* eri,
+                                      double e0, tdmps_mpo* out);
+/* One-body operator sum_pq t_pq a+_{p s} a_{q s} (e.g. the dipole operator). */
+tdmps_status tdmps_mpo_one_body(tdmps_ctx ctx, int32_t L, const double* t, tdmps_mpo* out);
+/* Replace the one-body integrals of an MPO in place (time-dependent H(t) = H0 + E(t) mu). */
+tdmps_status tdmps_mpo_set_one_body(tdmps_mpo mpo, const double* h);
+/* MPO bond dimensions at the L+1 cuts. */
+tdmps_status tdmps_mpo_bond_dims(tdmps_mpo mpo, int32_t* out);
+/* Host-only checks: the dense 4^L x 4^L matrix (row-major, L <= 6) and <bra|H|ket> between
+ * two determinants given as occupation codes. */
+tdmps_status tdmps_mpo_to_dense(tdmps_mpo mpo, double* out, int64_t len);
+tdmps_status tdmps_mpo_det_element(tdmps_mpo mpo, const uint8_t* bra, const uint8_t* ket, double* out);
+tdmps_status tdmps_mpo_destroy(tdmps_mpo mpo);
+
+/* ---------------------------------------------------------------- states (Eq. (mps))
+ * Product state of one determinant; occ[p] in {0,1,2,3} (bit0 = up, bit1 = down). */
+tdmps_status tdmps_mps_from_determinant(tdmps_ctx ctx, int32_t L, const uint8_t* occ, tdmps_mps* out);
+/* General block-sparse state.  bond_nsec[i] (i = 0..L) sectors per bond; bond_sec lists
+ * (n_up, n_dn, dim) for all sectors, bond by bond (bond 0 must be (0,0,1), bond L the
+ * total charge with dim 1).  data holds the site tensors one after another in the panel
+ * layout described above (interleaved complex); len = number of doubles. */
+tdmps_status tdmps_mps_from_blocks(tdmps_ctx ctx, int32_t L, const int32_t* bond_nsec, const int32_t* bond_sec,
+                                   const double* data, int64_t len, tdmps_mps* out);
+/* Sector tables: writes L+1 counts into bond_nsec and 3 ints per sector into bond_sec
+ * (either may be NULL to query *total_sectors first). */
+tdmps_status tdmps_mps_sectors(tdmps_mps mps, int32_t* bond_nsec, int32_t* bond_sec, int64_t* total_sectors);
+/* Site tensors in the panel layout (len doubles; query with data = NULL). */
+tdmps_status tdmps_mps_get_blocks(tdmps_mps mps, double* data, int64_t* len);
+/* Dense 4^L coefficient vector (interleaved complex, len = 2*4^L; L <= 12). */
+tdmps_status tdmps_mps_to_dense(tdmps_mps mps, double* out, int64_t len);
+tdmps_status tdmps_mps_copy(tdmps_mps mps, tdmps_mps* out);
+tdmps_status tdmps_mps_bond_dims(tdmps_mps mps, int32_t* out);
+tdmps_status tdmps_mps_destroy(tdmps_mps mps);
+
+/* ---------------------------------------------------------------- operations
+ * Scaling (Operations on MPS): multiplies one site tensor by alpha (re, im), in place. */
+tdmps_status tdmps_mps_scale(tdmps_mps mps, const double* alpha);
+/* <a|b> (re, im). */
+tdmps_status tdmps_mps_overlap(tdmps_mps a, tdmps_mps b, double* out);
+/* <bra|O|ket> (re, im) for an MPO O. */
+tdmps_status tdmps_mps_expect(tdmps_mpo op, tdmps_mps bra, tdmps_mps ket, double* out);
+/* Variational fit (Eq. (add_min)): out ~ alpha H psi + sum_j beta_j phi_j with bonds <= Dmax.
+ * alpha: (re, im); beta: 2*nterms doubles; phi: nterms states (may be 0).  The initial
+ * guess is psi, right-canonicalised.  info may be NULL. */
+tdmps_status tdmps_mps_apply_H(tdmps_mpo H, const double* alpha, tdmps_mps psi, int32_t nterms, const double* beta,
+                               const tdmps_mps* phi, const tdmps_fit_params* prm, tdmps_mps* out,
+                               tdmps_fit_info* info);
+/* MPS addition by the same fit: out ~ sum_j beta_j phi_j (nterms >= 1); the initial
+ * guess is phi[0], right-canonicalised. */
+tdmps_status tdmps_mps_compress(int32_t nterms, const double* beta, const tdmps_mps* phi,
+                                const tdmps_fit_params* prm, tdmps_mps* out, tdmps_fit_info* info);
+
+/* ---------------------------------------------------------------- time steps
+ * Krylov step (Eqs. (kry_orth)/(kry_non), (krylov_evo)): basis of m states, the first
+ * psi/|psi|; each next one fitted from H phi^k (minus the projections on all previous
+ * vectors for TDMPS_KRYLOV_ORTHO) and normalised; N and H from overlaps and sandwiches;
+ * out ~ |psi| sum_k [exp(-i dt N^-1 H)]_{k0} phi^k.  Nmat/Hmat (m*m interleaved complex,
+ * row-major) may be NULL.  Returns TDMPS_ERR_SINGULAR if N is not positive definite. */
+tdmps_status tdmps_krylov_step(tdmps_mpo H, tdmps_mps psi, double dt, int32_t m, int32_t flags,
+                               const tdmps_fit_params* prm, tdmps_mps* out, double* Nmat, double* Hmat);
+/* RK4 step (Eqs. (k1-k4), (rk_add)) with k_s = -i dt H(t_s) u_s fitted, u_s compressed:
+ * four H applications and four additions.  H_t, H_mid, H_t1 are the operators at t,
+ * t + dt/2 and t + dt (pass the same handle three times for a static H). */
+tdmps_status tdmps_rk4_step(tdmps_mpo H_t, tdmps_mpo H_mid, tdmps_mpo H_t1, tdmps_mps psi, double dt,
+                            const tdmps_fit_params* prm, tdmps_mps* out, tdmps_fit_info* info);
+
+/* ---------------------------------------------------------------- kernel-level access
+ * The two-site effective Hamiltonian at bond (site, site+1) between bra and ket states
+ * (the local operator of the fit): builds the left environment of sites < site and the
+ * right environment of sites > site+1 once; apply() then maps a ket two-site tensor
+ * theta[a, n1, n2, b] to sum L W W R theta in the bra layout.  Two-site tensors use the
+ * panel layout with blocks ordered (n1, n2) = (0,0), (0,1), ..., (3,3). */
+tdmps_status tdmps_heff_create(tdmps_mpo H, tdmps_mps bra, tdmps_mps ket, int32_t site, int32_t precision,
+                               tdmps_heff* out);
+/* Layout of the ket (which = 0) or bra (which = 1) two-site tensor: total doubles and the
+ * number of blocks; blocks (may be NULL) receives per block (n_up_a, n_dn_a, n1, n2, D_a,
+ * D_b, offset_in_doubles_lo, offset_hi, ld). */
+tdmps_status tdmps_heff_layout(tdmps_heff op, int32_t which, int64_t* total_doubles, int64_t* nblocks,
+                               int32_t* blocks);
+/* theta_out = H_eff theta_in; both device pointers (FP64 interleaved complex). */
+tdmps_status tdmps_heff_apply(tdmps_heff op, const void* theta_in_dev, void* theta_out_dev);
+/* Algorithmic flops of one apply (8 per complex multiply-add of the block products). */
+tdmps_status tdmps_heff_flops(tdmps_heff op, double* flops);
+tdmps_status tdmps_heff_destroy(tdmps_heff op);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDMPS_H */

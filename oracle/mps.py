@@ -11,7 +11,8 @@ order.
 Truncation (Methods, "MPS" paragraph): keep the D largest singular values.  Reading used
 for the points the paper leaves open: singular values of all charge sectors are sorted
 together (value descending, then sector in lexicographic (n_up, n_dn) order, then index);
-at most D are kept and only those above svd_cutoff * sigma_max (never fewer than one);
+at most D are kept and only those above svd_cutoff * sigma_max (default 1e-12, the
+numerical rank of an FP64 SVD of the sector sizes used; never fewer than one);
 nothing is renormalised.
 
 Variational fit (Methods, Eq. (add_min)): C approximates a target |T> = alpha H|psi> +
@@ -52,6 +53,7 @@ class FitInfo:
     sweeps: int = 0
     norm2: list = field(default_factory=list)
     discarded: list = field(default_factory=list)
+    min_gap: float = 1.0
 
 
 def from_occ(occ):
@@ -80,10 +82,17 @@ def _key(q):
     return (int(q[0]), int(q[1]))
 
 
+LAST_GAP = [1.0]
+GAP_LOG = []  # every truncation gap of fits since the last reset (test diagnostics)
+
+
 def sector_svd(M, row_q, col_q, Dmax, cutoff):
     """Charge-sector SVD of M with the global truncation rule.
 
-    Returns U (R x k), S (k), Vh (k x C), labels (k x 2), discarded weight."""
+    Returns U (R x k), S (k), Vh (k x C), labels (k x 2), discarded weight.  The relative
+    gap at the cut, (sigma_D - sigma_{D+1}) / sigma_D, is stored in LAST_GAP[0]; parity of a
+    truncated result with another SVD implementation is only well posed when it is not
+    tiny (reading c10 of the design notes)."""
     R, C = M.shape
     sectors = sorted(set(map(_key, row_q)) & set(map(_key, col_q)))
     rk = [_key(q) for q in row_q]
@@ -102,6 +111,11 @@ def sector_svd(M, row_q, col_q, Dmax, cutoff):
     keep = [c for c in cand if -c[0] > cutoff * smax][:Dmax]
     if not keep and cand:
         keep = cand[:1]
+    LAST_GAP[0] = 1.0
+    if len(keep) < len(cand) and -keep[-1][0] > 0:
+        nxt = -cand[len(keep)][0]
+        if nxt > cutoff * smax:  # a genuine truncation, not the numerical-rank cut
+            LAST_GAP[0] = (-keep[-1][0] - nxt) / -keep[-1][0]
     keep_set = set((c[1], c[2]) for c in keep)
     disc = sum(c[0] ** 2 for c in cand if (c[1], c[2]) not in keep_set)
     cols_u, svals, rows_v, labs = [], [], [], []
@@ -130,7 +144,7 @@ def _config_charges(nsites):
     return q
 
 
-def from_full(vec, L, Q, Dmax=10 ** 9, cutoff=1e-14):
+def from_full(vec, L, Q, Dmax=10 ** 9, cutoff=1e-12):
     """Sequential SVD decomposition of a full-space vector of total charge Q
     (Methods: the decomposition exists by reshaping and successive SVDs)."""
     Q = np.asarray(Q, dtype=np.int64)
@@ -156,7 +170,7 @@ def from_full(vec, L, Q, Dmax=10 ** 9, cutoff=1e-14):
     return MPS(tensors, labels), disc
 
 
-def right_canonicalize(mps: MPS, cutoff=1e-14):
+def right_canonicalize(mps: MPS, cutoff=1e-12):
     """Sweep right to left with sector SVDs; sites 1..L-1 become right-orthonormal and
     site 0 holds the norm (no truncation beyond the cutoff)."""
     m = mps.copy()
@@ -190,7 +204,7 @@ def _right_basis(m: MPS, i):
     return v  # (D_i, 4^(L-i))
 
 
-def fit(target, init: MPS, Dmax, n_sweeps=2, cutoff=1e-14, conv_tol=0.0):
+def fit(target, init: MPS, Dmax, n_sweeps=2, cutoff=1e-12, conv_tol=0.0):
     """Two-site variational fit of a dense target (replica of the local solves)."""
     L = init.L
     C = right_canonicalize(init, cutoff)
@@ -211,6 +225,8 @@ def fit(target, init: MPS, Dmax, n_sweeps=2, cutoff=1e-14, conv_tol=0.0):
                 cq = (C.labels[i + 2][None, :, :] - QLOC[:, None, :]).reshape(-1, 2)
                 U, S, Vh, lab, d = sector_svd(M, rq, cq, Dmax, cutoff)
                 info.discarded.append(d)
+                info.min_gap = min(info.min_gap, LAST_GAP[0])
+                GAP_LOG.append(LAST_GAP[0])
                 k = len(S)
                 if direction == "lr":
                     C.tensors[i] = U.reshape(Dl, 4, k)
@@ -243,7 +259,7 @@ class DenseOps:
 
     Hfull(v) applies the Hamiltonian to a full Fock-space vector."""
 
-    def __init__(self, Hfull, Dmax, n_sweeps=2, cutoff=1e-14):
+    def __init__(self, Hfull, Dmax, n_sweeps=2, cutoff=1e-12):
         self.H = Hfull
         self.Dmax, self.n_sweeps, self.cutoff = Dmax, n_sweeps, cutoff
 

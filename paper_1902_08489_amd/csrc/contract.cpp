@@ -1,0 +1,625 @@
+// Environment updates and the two-site effective Hamiltonian as grouped block GEMMs.
+//
+// Notation: L_w[a, a'] (bra a, ket a') is the left environment of MPO channel w at a cut,
+// R_u[b, b'] the right one; W_p[w -> v] |s><s'| the MPO site tensors; theta[a, s1, s2, b]
+// a two-site tensor.  The two-site local operator of the fit (Methods, Eq. (add_min)) is
+//   theta_out[a s1 s2 b] = sum L_w[a a'] W_i[w v s1 s1'] W_{i+1}[v u s2 s2'] R_u[b b'] theta[a' s1' s2' b'].
+// It is evaluated through the channels v of the middle cut:
+//   Lop_v^{s1 s1'} = sum_w W_i[w v s1 s1'] L_w,   Rop_v^{s2 s2'} = sum_u W_{i+1}[v u s2 s2'] R_u,
+//   T_v[a s1 s2' b'] = sum_{s1'} Lop_v^{s1 s1'} theta[s1' s2'],
+//   theta_out[a s1 s2 b] = sum_v sum_{s2'} T_v[a s1 s2' b'] Rop_v^{s2 s2' T}[b' b].
+// Single-source operators alias the environment (pass-through channels, new single
+// operators); multi-source ones (complementary sums) are formed once as a real-coefficient
+// GEMM over the channel index.  Consecutive middle channels with the same structure form
+// "runs" whose blocks are stacked, so each block product is one batched GEMM over a run.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+#include "engine.h"
+
+namespace tdmps {
+namespace {
+
+const cplx ONE{1.0, 0.0};
+
+struct Run {
+  int v0, n;
+};
+
+// channel-ordered W entries grouped by the "middle" channel
+struct MixGroupKey {
+  int pat, vcls;
+  bool operator<(const MixGroupKey& o) const { return std::tie(pat, vcls) < std::tie(o.pat, o.vcls); }
+};
+
+struct MixRow {
+  int v;
+  std::vector<std::pair<int, double>> src;  // (source channel, coefficient)
+};
+
+SideOps build_ops(Contractor& C, const Env& E, const MpoHost& W, int site, bool left) {
+  SideOps ops;
+  const int mid_cut = left ? site + 1 : site;
+  const MpoCut& mc = W.cut[mid_cut];
+  const MpoCut& sc = W.cut[E.cut];
+  ops.cut = mid_cut;
+  ops.env = &E;
+  ops.ch.resize(mc.size());
+  // per middle channel, per pattern: list of (source channel, coefficient)
+  std::vector<std::map<int, std::vector<std::pair<int, double>>>> per(mc.size());
+  for (const auto& e : W.W[site]) {
+    int mid = left ? e.v : e.w;
+    int src = left ? e.w : e.v;
+    per[mid][e.s * 4 + e.sp].push_back({src, e.c});
+  }
+  std::map<MixGroupKey, std::vector<MixRow>> mix;
+  for (int v = 0; v < mc.size(); ++v) {
+    for (auto& kv : per[v]) {
+      ops.ch[v].pat.push_back(kv.first);
+      OpRef r;
+      if (kv.second.size() == 1) {
+        int w = kv.second[0].first;
+        r.src = &E.b;
+        r.grp = sc.cls_of[w];
+        r.idx = w - sc.cls_start[r.grp];
+        r.coef = kv.second[0].second;
+      } else {
+        r.src = nullptr;  // filled below
+        mix[{kv.first, mc.cls_of[v]}].push_back({v, kv.second});
+      }
+      ops.ch[v].ref.push_back(r);
+    }
+  }
+  if (mix.empty()) return ops;
+  // premix layout: one group per (pattern, middle class)
+  std::vector<std::pair<Charge, int>> groups;
+  std::vector<int> src_cls;
+  for (auto& kv : mix) {
+    int w0 = kv.second[0].src[0].first;
+    int cw = sc.cls_of[w0];
+    for (auto& row : kv.second)
+      for (auto& s : row.src)
+        TDMPS_REQUIRE(sc.cls_of[s.first] == cw, TDMPS_ERR_NUMERIC, "internal: premix sources differ in charge");
+    groups.push_back({sc.cls_q[cw], (int)kv.second.size()});
+    src_cls.push_back(cw);
+  }
+  ops.mix.reset(new Blocks());
+  ops.mix->layout(E.b.bra, E.b.ket, groups);
+  ops.mix->data = DevBuf(ops.mix->size * sizeof(cplx));
+  // coefficient matrices (dense over the used source range) and GEMMs per ket sector
+  std::vector<cplx> wmat;
+  struct Pending {
+    int g, cw, wlo, ncol;
+    size_t off;
+  };
+  std::vector<Pending> pend;
+  int g = 0;
+  for (auto& kv : mix) {
+    int cw = src_cls[g];
+    int lo = 1 << 30, hi = -1;
+    for (auto& row : kv.second)
+      for (auto& s : row.src) {
+        lo = std::min(lo, s.first);
+        hi = std::max(hi, s.first);
+      }
+    int ncol = hi - lo + 1;
+    size_t off = wmat.size();
+    wmat.resize(off + (size_t)kv.second.size() * ncol, cplx{0, 0});
+    for (size_t r = 0; r < kv.second.size(); ++r) {
+      for (auto& s : kv.second[r].src) wmat[off + r * ncol + (s.first - lo)].x += s.second;
+      int v = kv.second[r].v;
+      for (size_t k = 0; k < ops.ch[v].pat.size(); ++k)
+        if (ops.ch[v].pat[k] == kv.first.pat) {
+          ops.ch[v].ref[k].src = ops.mix.get();
+          ops.ch[v].ref[k].grp = g;
+          ops.ch[v].ref[k].idx = (int)r;
+          ops.ch[v].ref[k].coef = 1.0;
+        }
+    }
+    pend.push_back({g, cw, lo - sc.cls_start[cw], ncol, off});
+    ++g;
+  }
+  Staging st;
+  const cplx* dw = st.put(C.ctx, wmat);
+  GemmPlan plan;
+  const Blocks& eb = E.b;
+  for (auto& p : pend) {
+    const StackGroup& sg = ops.mix->grp[p.g];
+    for (int ks = 0; ks < eb.ket.nsec(); ++ks) {
+      if (sg.off[ks] < 0) continue;
+      int bs = sg.bra_of[ks];
+      int64_t blk = (int64_t)eb.bra.dim[bs] * eb.ket.dim[ks];
+      const cplx* B = eb.stack(p.cw, ks);
+      TDMPS_REQUIRE(B != nullptr, TDMPS_ERR_NUMERIC, "internal: premix source stack missing");
+      plan.begin_task(ops.mix->stack(p.g, ks), 0, (int)blk, sg.n, (int)blk, 1, false);
+      plan.add_seg(dw + p.off, 0, 0, p.ncol, OP_N, B + (int64_t)p.wlo * blk, 0, 0, (int)blk, OP_N, p.ncol, 1, ONE);
+    }
+  }
+  plan.run(C.ctx, TDMPS_FP64);
+  C.mix_flops += plan.flops;
+  return ops;
+}
+
+bool same_structure(const ChanOps& a, const ChanOps& b) {
+  if (a.pat != b.pat) return false;
+  for (size_t k = 0; k < a.pat.size(); ++k) {
+    const OpRef &x = a.ref[k], &y = b.ref[k];
+    if (x.src != y.src || x.grp != y.grp || x.idx + 1 != y.idx || x.coef != y.coef) return false;
+  }
+  return true;
+}
+
+// Maximal ranges of middle channels with identical structure on the given sides.
+std::vector<Run> make_runs(const MpoCut& mc, const SideOps* a, const SideOps* b) {
+  std::vector<Run> runs;
+  int n = mc.size();
+  int v = 0;
+  while (v < n) {
+    int e = v + 1;
+    while (e < n && mc.cls_of[e] == mc.cls_of[v] && (!a || same_structure(a->ch[e - 1], a->ch[e])) &&
+           (!b || same_structure(b->ch[e - 1], b->ch[e])))
+      ++e;
+    runs.push_back({v, e - v});
+    v = e;
+  }
+  return runs;
+}
+
+inline cplx cmul(cplx a, cplx b) { return cplx{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+
+}  // namespace
+
+SideOps premix_left(Contractor& C, const Env& L, const MpoHost& W, int site) {
+  TDMPS_REQUIRE(L.cut == site, TDMPS_ERR_ARG, "internal: left environment cut");
+  return build_ops(C, L, W, site, true);
+}
+
+SideOps premix_right(Contractor& C, const Env& R, const MpoHost& W, int site) {
+  TDMPS_REQUIRE(R.cut == site + 1, TDMPS_ERR_ARG, "internal: right environment cut");
+  return build_ops(C, R, W, site, false);
+}
+
+Env env_left_boundary(Ctx* ctx, const Bond& bra0, const Bond& ket0) {
+  Env E;
+  E.cut = 0;
+  E.b.layout(bra0, ket0, {{Charge(0, 0), 1}});
+  E.b.data = DevBuf(sizeof(cplx));
+  cplx one{1.0, 0.0};
+  dev_h2d(E.b.data.p, &one, sizeof(cplx), ctx->stream);
+  return E;
+}
+
+Env env_right_boundary(Ctx* ctx, const Bond& braL, const Bond& ketL, int L) {
+  TDMPS_REQUIRE(braL.q[0] == ketL.q[0], TDMPS_ERR_SECTOR, "bra and ket have different total charge");
+  Env E;
+  E.cut = L;
+  E.b.layout(braL, ketL, {{Charge(0, 0), 1}});
+  E.b.data = DevBuf(sizeof(cplx));
+  cplx one{1.0, 0.0};
+  dev_h2d(E.b.data.p, &one, sizeof(cplx), ctx->stream);
+  return E;
+}
+
+static std::vector<std::pair<Charge, int>> cut_groups(const MpoCut& c) {
+  std::vector<std::pair<Charge, int>> g;
+  for (size_t k = 0; k < c.cls_q.size(); ++k) g.push_back({c.cls_q[k], c.cls_count[k]});
+  return g;
+}
+
+Env env_left_update(Contractor& C, const SideOps& ops, const Mps*, const cplx* bra_site, const SiteLayout& bl,
+                    const Bond& bra_l, const Bond& bra_r, const cplx* ket_site, const SiteLayout& kl,
+                    const Bond& ket_l, const Bond& ket_r, const MpoHost& W) {
+  const MpoCut& mc = W.cut[ops.cut];
+  Env out;
+  out.cut = ops.cut;
+  out.b.layout(bra_r, ket_r, cut_groups(mc));
+  out.b.data = DevBuf(out.b.size * sizeof(cplx));
+  if (out.b.size) dev_zero(out.b.data.p, out.b.data.bytes, C.ctx->stream);
+  auto runs = make_runs(mc, &ops, nullptr);
+  // T_v[s, sig, t'] = sum_{sig'} Lop_v^{sig sig'}[s, s'] A_ket[s', sig', t']
+  struct TKey {
+    int r, s, sig, tk;
+  };
+  std::vector<TKey> tkeys;
+  std::vector<int64_t> toff;
+  int64_t tsize = 0;
+  std::map<std::tuple<int, int, int, int>, int> tindex;
+  for (int r = 0; r < (int)runs.size(); ++r) {
+    int v0 = runs[r].v0;
+    int g = mc.cls_of[v0];
+    const StackGroup& og = out.b.grp[g];
+    for (int tk = 0; tk < ket_r.nsec(); ++tk) {
+      int tb = og.bra_of[tk];
+      if (tb < 0) continue;
+      for (int s = 0; s < bra_l.nsec(); ++s)
+        for (int sig = 0; sig < 4; ++sig) {
+          if (bl.rs[s][sig] != tb) continue;
+          tindex[{r, s, sig, tk}] = (int)tkeys.size();
+          tkeys.push_back({r, s, sig, tk});
+          toff.push_back(tsize);
+          tsize += (int64_t)runs[r].n * bra_l.dim[s] * ket_r.dim[tk];
+        }
+    }
+  }
+  DevBuf T(tsize * sizeof(cplx));
+  GemmPlan p1;
+  std::vector<char> tnonzero(tkeys.size(), 0);
+  for (size_t t = 0; t < tkeys.size(); ++t) {
+    const TKey& K = tkeys[t];
+    const Run& run = runs[K.r];
+    const ChanOps& co = ops.ch[run.v0];
+    int Ds = bra_l.dim[K.s], Dt = ket_r.dim[K.tk];
+    bool started = false;
+    for (size_t k = 0; k < co.pat.size(); ++k) {
+      int sig = co.pat[k] >> 2, sigp = co.pat[k] & 3;
+      if (sig != K.sig) continue;
+      const OpRef& ref = co.ref[k];
+      const StackGroup& sg = ref.src->grp[ref.grp];
+      int sp = sg.ket_of[K.s];
+      if (sp < 0) continue;
+      if (kl.rs[sp][sigp] != K.tk) continue;
+      int Dsp = ket_l.dim[sp];
+      if (!started) {
+        p1.begin_task(T.c() + toff[t], 0, Dt, run.n * Ds, Dt, 1, false);
+        started = true;
+      }
+      const cplx* A = ref.src->stack(ref.grp, sp) + (int64_t)ref.idx * Ds * Dsp;
+      const cplx* B = ket_site + kl.panel_off[sp] + kl.col[sp][sigp];
+      p1.add_seg(A, 0, 0, Dsp, OP_N, B, 0, 0, kl.width[sp], OP_N, Dsp, 1, cplx{ref.coef, 0.0});
+    }
+    tnonzero[t] = started;
+  }
+  p1.run(C.ctx, C.precision);
+  // L'_v[t, t'] = sum_{s, sig} conj(C[s, sig, t])^T T_v[s, sig, t']
+  GemmPlan p2;
+  for (int r = 0; r < (int)runs.size(); ++r) {
+    int v0 = runs[r].v0;
+    int g = mc.cls_of[v0];
+    int j0 = v0 - mc.cls_start[g];
+    const StackGroup& og = out.b.grp[g];
+    for (int tk = 0; tk < ket_r.nsec(); ++tk) {
+      int tb = og.bra_of[tk];
+      if (tb < 0) continue;
+      int Dt = bra_r.dim[tb], Dtk = ket_r.dim[tk];
+      bool started = false;
+      for (int s = 0; s < bra_l.nsec(); ++s)
+        for (int sig = 0; sig < 4; ++sig) {
+          if (bl.rs[s][sig] != tb) continue;
+          auto it = tindex.find({r, s, sig, tk});
+          if (it == tindex.end() || !tnonzero[it->second]) continue;
+          int Ds = bra_l.dim[s];
+          if (!started) {
+            p2.begin_task(out.b.stack(g, tk) + (int64_t)j0 * Dt * Dtk, (int64_t)Dt * Dtk, Dtk, Dt, Dtk, runs[r].n,
+                          true);
+            started = true;
+          }
+          const cplx* A = bra_site + bl.panel_off[s] + bl.col[s][sig];
+          p2.add_seg(A, 0, 0, bl.width[s], OP_C, T.c() + toff[it->second], (int64_t)Ds * Dtk, 0, Dtk, OP_N, Ds, 1,
+                     ONE);
+        }
+    }
+  }
+  p2.run(C.ctx, C.precision);
+  C.env_flops += p1.flops + p2.flops;
+  return out;
+}
+
+Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, const SiteLayout& bl, const Bond& bra_l,
+                     const Bond& bra_r, const cplx* ket_site, const SiteLayout& kl, const Bond& ket_l,
+                     const Bond& ket_r, const MpoHost& W) {
+  const MpoCut& mc = W.cut[ops.cut];
+  Env out;
+  out.cut = ops.cut;
+  out.b.layout(bra_l, ket_l, cut_groups(mc));
+  out.b.data = DevBuf(out.b.size * sizeof(cplx));
+  if (out.b.size) dev_zero(out.b.data.p, out.b.data.bytes, C.ctx->stream);
+  auto runs = make_runs(mc, &ops, nullptr);
+  // T_v[s', sig, t] = sum_{sig'} A_ket[s', sig', t'] Rop_v^{sig sig'}[t, t']^T
+  struct TKey {
+    int r, sk, sig, tb;
+  };
+  std::vector<TKey> tkeys;
+  std::vector<int64_t> toff;
+  int64_t tsize = 0;
+  std::map<std::tuple<int, int, int, int>, int> tindex;
+  for (int r = 0; r < (int)runs.size(); ++r) {
+    int g = mc.cls_of[runs[r].v0];
+    const StackGroup& og = out.b.grp[g];
+    for (int sk = 0; sk < ket_l.nsec(); ++sk) {
+      int sb = og.bra_of[sk];
+      if (sb < 0) continue;
+      for (int sig = 0; sig < 4; ++sig) {
+        int tb = bl.rs[sb][sig];
+        if (tb < 0) continue;
+        tindex[{r, sk, sig, tb}] = (int)tkeys.size();
+        tkeys.push_back({r, sk, sig, tb});
+        toff.push_back(tsize);
+        tsize += (int64_t)runs[r].n * ket_l.dim[sk] * bra_r.dim[tb];
+      }
+    }
+  }
+  DevBuf T(tsize * sizeof(cplx));
+  GemmPlan p1;
+  std::vector<char> tnonzero(tkeys.size(), 0);
+  for (size_t t = 0; t < tkeys.size(); ++t) {
+    const TKey& K = tkeys[t];
+    const Run& run = runs[K.r];
+    const ChanOps& co = ops.ch[run.v0];
+    int Dsk = ket_l.dim[K.sk], Dt = bra_r.dim[K.tb];
+    bool started = false;
+    for (size_t k = 0; k < co.pat.size(); ++k) {
+      int sig = co.pat[k] >> 2, sigp = co.pat[k] & 3;
+      if (sig != K.sig) continue;
+      const OpRef& ref = co.ref[k];
+      const StackGroup& sg = ref.src->grp[ref.grp];
+      int tk = sg.ket_of[K.tb];
+      if (tk < 0) continue;
+      if (kl.rs[K.sk][sigp] != tk) continue;
+      int Dtk = ket_r.dim[tk];
+      if (!started) {
+        p1.begin_task(T.c() + toff[t], (int64_t)Dsk * Dt, Dt, Dsk, Dt, run.n, false);
+        started = true;
+      }
+      const cplx* A = ket_site + kl.panel_off[K.sk] + kl.col[K.sk][sigp];
+      const cplx* B = ref.src->stack(ref.grp, tk) + (int64_t)ref.idx * Dt * Dtk;
+      p1.add_seg(A, 0, 0, kl.width[K.sk], OP_N, B, (int64_t)Dt * Dtk, 0, Dtk, OP_T, Dtk, 1, cplx{ref.coef, 0.0});
+    }
+    tnonzero[t] = started;
+  }
+  p1.run(C.ctx, C.precision);
+  // R'_v[s, s'] = sum_{sig, t} conj(C[s, sig, t]) T_v[s', sig, t]^T
+  GemmPlan p2;
+  for (int r = 0; r < (int)runs.size(); ++r) {
+    int v0 = runs[r].v0;
+    int g = mc.cls_of[v0];
+    int j0 = v0 - mc.cls_start[g];
+    const StackGroup& og = out.b.grp[g];
+    for (int sk = 0; sk < ket_l.nsec(); ++sk) {
+      int sb = og.bra_of[sk];
+      if (sb < 0) continue;
+      int Ds = bra_l.dim[sb], Dsk = ket_l.dim[sk];
+      bool started = false;
+      for (int sig = 0; sig < 4; ++sig) {
+        int tb = bl.rs[sb][sig];
+        if (tb < 0) continue;
+        auto it = tindex.find({r, sk, sig, tb});
+        if (it == tindex.end() || !tnonzero[it->second]) continue;
+        int Dt = bra_r.dim[tb];
+        if (!started) {
+          p2.begin_task(out.b.stack(g, sk) + (int64_t)j0 * Ds * Dsk, (int64_t)Ds * Dsk, Dsk, Ds, Dsk, runs[r].n, true);
+          started = true;
+        }
+        const cplx* A = bra_site + bl.panel_off[sb] + bl.col[sb][sig];
+        p2.add_seg(A, 0, 0, bl.width[sb], OP_J, T.c() + toff[it->second], (int64_t)Dsk * Dt, 0, Dt, OP_T, Dt, 1, ONE);
+      }
+    }
+  }
+  p2.run(C.ctx, C.precision);
+  C.env_flops += p1.flops + p2.flops;
+  return out;
+}
+
+void HeffPlan::launch(Ctx* ctx, int precision) {
+  if (!accumulate && out_size) dev_zero(out, out_size * sizeof(cplx), ctx->stream);
+  p1.launch(ctx, precision);
+  p2.launch(ctx, precision);
+}
+
+void heff_apply(Contractor& C, const SideOps& lops, const SideOps& rops, const cplx* theta_in, const TwoLayout& kl,
+                const Bond& ket_l, const Bond& ket_r, cplx* theta_out, const TwoLayout& bl, const Bond& bra_l,
+                const Bond& bra_r, cplx alpha, bool accumulate, double* alg_flops) {
+  auto plan = heff_plan(C, lops, rops, theta_in, kl, ket_l, ket_r, theta_out, bl, bra_l, bra_r, alpha, accumulate);
+  plan->launch(C.ctx, C.precision);
+  dev_sync(C.ctx->stream);
+  C.heff_flops += plan->p1.flops + plan->p2.flops;
+  if (alg_flops) *alg_flops = plan->alg_flops;
+}
+
+std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const SideOps& rops, const cplx* theta_in,
+                                    const TwoLayout& kl, const Bond& ket_l, const Bond& ket_r, cplx* theta_out,
+                                    const TwoLayout& bl, const Bond& bra_l, const Bond& bra_r, cplx alpha,
+                                    bool accumulate) {
+  TDMPS_REQUIRE(lops.cut == rops.cut, TDMPS_ERR_ARG, "internal: middle cuts differ");
+  auto plan = std::make_unique<HeffPlan>();
+  plan->out = theta_out;
+  plan->out_size = bl.size;
+  plan->accumulate = accumulate;
+  const int nmid = (int)lops.ch.size();
+  // runs over the middle cut with identical structure on both sides
+  std::vector<Run> runs;
+  {
+    int v = 0;
+    while (v < nmid) {
+      int e = v + 1;
+      while (e < nmid && same_structure(lops.ch[e - 1], lops.ch[e]) && same_structure(rops.ch[e - 1], rops.ch[e]))
+        ++e;
+      runs.push_back({v, e - v});
+      v = e;
+    }
+  }
+  // final stage segments per output block, collecting the T blocks they need
+  struct TKey {
+    int r, s, s1, s2p, tk;
+  };
+  std::map<std::tuple<int, int, int, int, int>, int> tindex;
+  std::vector<TKey> tkeys;
+  struct FSeg {
+    int tkey;
+    const OpRef* ref;
+    int tb;
+  };
+  std::vector<std::vector<FSeg>> fsegs;  // per output block
+  struct OBlk {
+    int s, sig, tb;
+  };
+  std::vector<OBlk> oblk;
+  for (int s = 0; s < bra_l.nsec(); ++s)
+    for (int sig = 0; sig < 16; ++sig) {
+      int tb = bl.rs[s][sig];
+      if (tb < 0) continue;
+      oblk.push_back({s, sig, tb});
+    }
+  fsegs.resize(oblk.size());
+  for (size_t ob = 0; ob < oblk.size(); ++ob) {
+    int s = oblk[ob].s, s1 = oblk[ob].sig >> 2, s2 = oblk[ob].sig & 3, tb = oblk[ob].tb;
+    for (int r = 0; r < (int)runs.size(); ++r) {
+      const ChanOps& ro = rops.ch[runs[r].v0];
+      for (size_t k = 0; k < ro.pat.size(); ++k) {
+        if ((ro.pat[k] >> 2) != s2) continue;
+        int s2p = ro.pat[k] & 3;
+        const OpRef& ref = ro.ref[k];
+        int tk = ref.src->grp[ref.grp].ket_of[tb];
+        if (tk < 0) continue;
+        auto key = std::make_tuple(r, s, s1, s2p, tk);
+        auto it = tindex.find(key);
+        int id;
+        if (it == tindex.end()) {
+          id = (int)tkeys.size();
+          tindex[key] = id;
+          tkeys.push_back({r, s, s1, s2p, tk});
+        } else {
+          id = it->second;
+        }
+        fsegs[ob].push_back({id, &ref, tb});
+      }
+    }
+  }
+  // T stage
+  std::vector<int64_t> toff(tkeys.size(), -1);
+  int64_t tsize = 0;
+  GemmPlan& p1 = plan->p1;
+  for (size_t t = 0; t < tkeys.size(); ++t) {
+    const TKey& K = tkeys[t];
+    const Run& run = runs[K.r];
+    const ChanOps& lo = lops.ch[run.v0];
+    int Ds = bra_l.dim[K.s], Dtk = ket_r.dim[K.tk];
+    bool started = false;
+    for (size_t k = 0; k < lo.pat.size(); ++k) {
+      if ((lo.pat[k] >> 2) != K.s1) continue;
+      int s1p = lo.pat[k] & 3;
+      const OpRef& ref = lo.ref[k];
+      int sk = ref.src->grp[ref.grp].ket_of[K.s];
+      if (sk < 0) continue;
+      int sig_in = s1p * 4 + K.s2p;
+      if (kl.rs[sk][sig_in] != K.tk) continue;
+      int Dsk = ket_l.dim[sk];
+      if (!started) {
+        toff[t] = tsize;
+        tsize += (int64_t)run.n * Ds * Dtk;
+        p1.begin_task(nullptr, 0, Dtk, run.n * Ds, Dtk, 1, false);
+        started = true;
+      }
+      const cplx* A = ref.src->stack(ref.grp, sk) + (int64_t)ref.idx * Ds * Dsk;
+      const cplx* B = theta_in + kl.panel_off[sk] + kl.col[sk][sig_in];
+      p1.add_seg(A, 0, 0, Dsk, OP_N, B, 0, 0, kl.width[sk], OP_N, Dsk, 1, cplx{ref.coef, 0.0});
+    }
+  }
+  plan->T = DevBuf(tsize * sizeof(cplx));
+  cplx* Tb = plan->T.c();
+  {
+    size_t ti = 0;
+    for (size_t t = 0; t < tkeys.size(); ++t)
+      if (toff[t] >= 0) p1.tasks[ti++].C = Tb + toff[t];
+  }
+  // final stage
+  GemmPlan& p2 = plan->p2;
+  double alg = 0;
+  for (size_t ob = 0; ob < oblk.size(); ++ob) {
+    int s = oblk[ob].s, sig = oblk[ob].sig, tb = oblk[ob].tb;
+    int Ds = bra_l.dim[s], Dt = bra_r.dim[tb];
+    bool started = false;
+    for (auto& fs : fsegs[ob]) {
+      if (toff[fs.tkey] < 0) continue;
+      const TKey& K = tkeys[fs.tkey];
+      const Run& run = runs[K.r];
+      int Dtk = ket_r.dim[K.tk];
+      if (!started) {
+        p2.begin_task(theta_out + bl.panel_off[s] + bl.col[s][sig], 0, bl.width[s], Ds, Dt, 1, true);
+        started = true;
+      }
+      const OpRef& ref = *fs.ref;
+      const cplx* A = Tb + toff[fs.tkey];
+      const cplx* B = ref.src->stack(ref.grp, K.tk) + (int64_t)ref.idx * Dt * Dtk;
+      p2.add_seg(A, 0, (int64_t)Ds * Dtk, Dtk, OP_N, B, 0, (int64_t)Dt * Dtk, Dtk, OP_T, Dtk, run.n,
+                 cmul(cplx{ref.coef, 0.0}, alpha));
+    }
+  }
+  // algorithmic count in the plain order (L theta) -> W -> (. R): every channel of the outer
+  // cuts against every compatible block.
+  {
+    const Blocks& Lb = lops.env->b;
+    const Blocks& Rb = rops.env->b;
+    for (const auto& g : Lb.grp)
+      for (int sk = 0; sk < ket_l.nsec(); ++sk) {
+        int sb = g.bra_of[sk];
+        if (sb < 0) continue;
+        for (int sig = 0; sig < 16; ++sig) {
+          int tk = kl.rs[sk][sig];
+          if (tk < 0) continue;
+          alg += 8.0 * g.n * bra_l.dim[sb] * (double)ket_l.dim[sk] * ket_r.dim[tk];
+        }
+      }
+    for (const auto& g : Rb.grp)
+      for (int s = 0; s < bra_l.nsec(); ++s)
+        for (int sig = 0; sig < 16; ++sig) {
+          int tb = bl.rs[s][sig];
+          if (tb < 0) continue;
+          int tk = g.ket_of[tb];
+          if (tk < 0) continue;
+          alg += 8.0 * g.n * bra_l.dim[s] * (double)bra_r.dim[tb] * ket_r.dim[tk];
+        }
+    plan->alg_flops = alg;
+  }
+  p1.finalize(C.ctx);
+  p2.finalize(C.ctx);
+  return plan;
+}
+
+void form_theta(Contractor& C, const Mps* m, int i, cplx* theta, const TwoLayout& tl) {
+  const SiteLayout& a = m->lay[i];
+  const SiteLayout& b = m->lay[i + 1];
+  const Bond& l = m->bond[i];
+  if (tl.size) dev_zero(theta, tl.size * sizeof(cplx), C.ctx->stream);
+  GemmPlan p;
+  for (int s = 0; s < l.nsec(); ++s)
+    for (int s1 = 0; s1 < 4; ++s1) {
+      int mid = a.rs[s][s1];
+      if (mid < 0) continue;
+      for (int s2 = 0; s2 < 4; ++s2) {
+        int t = b.rs[mid][s2];
+        if (t < 0) continue;
+        int sig = s1 * 4 + s2;
+        TDMPS_REQUIRE(tl.rs[s][sig] == t, TDMPS_ERR_NUMERIC, "internal: two-site layout mismatch");
+        p.begin_task(theta + tl.panel_off[s] + tl.col[s][sig], 0, tl.width[s], l.dim[s], m->bond[i + 2].dim[t], 1,
+                     false);
+        p.add_seg(m->site[i].c() + a.panel_off[s] + a.col[s][s1], 0, 0, a.width[s], OP_N,
+                  m->site[i + 1].c() + b.panel_off[mid] + b.col[mid][s2], 0, 0, b.width[mid], OP_N,
+                  m->bond[i + 1].dim[mid], 1, ONE);
+      }
+    }
+  p.run(C.ctx, TDMPS_FP64);
+}
+
+cplx sandwich(Contractor& C, const MpoHost& O, const Mps* bra, const Mps* ket) {
+  TDMPS_REQUIRE(bra->L == ket->L && bra->L == O.L, TDMPS_ERR_ARG, "length mismatch");
+  TDMPS_REQUIRE(bra->total == ket->total, TDMPS_ERR_SECTOR, "bra and ket have different total charge");
+  Env E = env_left_boundary(C.ctx, bra->bond[0], ket->bond[0]);
+  for (int i = 0; i < bra->L; ++i) {
+    SideOps ops = premix_left(C, E, O, i);
+    Env N = env_left_update(C, ops, bra, bra->site[i].c(), bra->lay[i], bra->bond[i], bra->bond[i + 1],
+                            ket->site[i].c(), ket->lay[i], ket->bond[i], ket->bond[i + 1], O);
+    E = std::move(N);
+  }
+  cplx out{0, 0};
+  if (E.b.size) dev_d2h(&out, E.b.data.p, sizeof(cplx), C.ctx->stream);
+  return out;
+}
+
+cplx overlap(Contractor& C, const Mps* a, const Mps* b) {
+  MpoHost I = identity_mpo(a->L);
+  return sandwich(C, I, a, b);
+}
+
+}  // namespace tdmps

@@ -1,0 +1,155 @@
+// HIP runtime layer: device selection, a caching device allocator, copies, streams,
+// events and fill kernels.  All device memory of the library is ordered on the stream of
+// its context, so a freed block can be handed to later work on that stream at once.
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace tdmps {
+namespace {
+
+void check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Error(TDMPS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+std::mutex g_mu;
+std::multimap<size_t, void*> g_free;
+std::unordered_map<void*, size_t> g_size;
+
+size_t round_size(size_t b) {
+  if (b < (1u << 20)) return (b + 511) & ~size_t(511);
+  return (b + (2u << 20) - 1) & ~((size_t(2) << 20) - 1);
+}
+
+void release_cache() {
+  for (auto& kv : g_free) {
+    g_size.erase(kv.second);
+    (void)hipFree(kv.second);
+  }
+  g_free.clear();
+}
+
+__global__ void fill_zero(uint4* p, size_t n16, unsigned char* tail, size_t ntail) {
+  size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t k = i; k < n16; k += stride) p[k] = make_uint4(0, 0, 0, 0);
+  if (i < ntail) tail[i] = 0;
+}
+
+__global__ void scale_kernel(double2* x, int64_t n, double ar, double ai) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = i; k < n; k += stride) {
+    double2 v = x[k];
+    x[k] = make_double2(v.x * ar - v.y * ai, v.x * ai + v.y * ar);
+  }
+}
+
+}  // namespace
+
+void dev_set_device(int device) { check(hipSetDevice(device), "hipSetDevice"); }
+
+void* dev_alloc(size_t bytes) {
+  size_t b = round_size(bytes);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_free.lower_bound(b);
+  if (it != g_free.end() && it->first <= b + b / 4 + (4u << 20)) {
+    void* p = it->second;
+    g_free.erase(it);
+    return p;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, b) != hipSuccess) {
+    (void)hipGetLastError();
+    release_cache();
+    p = nullptr;
+    if (hipMalloc(&p, b) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+  }
+  g_size[p] = b;
+  return p;
+}
+
+void dev_free(void* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_size.find(p);
+  if (it == g_size.end()) return;
+  g_free.emplace(it->second, p);
+}
+
+void dev_h2d(void* dst, const void* src, size_t bytes, void* stream) {
+  if (!bytes) return;
+  check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, (hipStream_t)stream), "hipMemcpyAsync H2D");
+}
+
+void dev_d2h(void* dst, const void* src, size_t bytes, void* stream) {
+  if (!bytes) return;
+  check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, (hipStream_t)stream), "hipMemcpyAsync D2H");
+  check(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+}
+
+void dev_d2d(void* dst, const void* src, size_t bytes, void* stream) {
+  if (!bytes) return;
+  check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream), "hipMemcpyAsync D2D");
+}
+
+void dev_zero(void* dst, size_t bytes, void* stream) {
+  if (!bytes) return;
+  size_t n16 = bytes / 16, ntail = bytes % 16;
+  int threads = 256;
+  size_t blocks = (n16 + threads - 1) / threads;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(fill_zero, dim3((unsigned)blocks), dim3(threads), 0, (hipStream_t)stream, (uint4*)dst, n16,
+                     (unsigned char*)dst + n16 * 16, ntail);
+  check(hipGetLastError(), "fill_zero launch");
+}
+
+void launch_scale(cplx* x, int64_t n, cplx alpha, void* stream) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(scale_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, (double2*)x, n, alpha.x,
+                     alpha.y);
+  check(hipGetLastError(), "scale launch");
+}
+
+void dev_sync(void* stream) { check(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize"); }
+
+void* dev_stream_create() {
+  hipStream_t s;
+  check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+  return s;
+}
+
+void dev_stream_destroy(void* s) { (void)hipStreamDestroy((hipStream_t)s); }
+
+void* dev_event_create() {
+  hipEvent_t e;
+  check(hipEventCreate(&e), "hipEventCreate");
+  return e;
+}
+
+void dev_event_destroy(void* e) { (void)hipEventDestroy((hipEvent_t)e); }
+
+void dev_event_record(void* e, void* stream) {
+  check(hipEventRecord((hipEvent_t)e, (hipStream_t)stream), "hipEventRecord");
+}
+
+float dev_event_elapsed_ms(void* a, void* b) {
+  check(hipEventSynchronize((hipEvent_t)b), "hipEventSynchronize");
+  float ms = 0;
+  check(hipEventElapsedTime(&ms, (hipEvent_t)a, (hipEvent_t)b), "hipEventElapsedTime");
+  return ms;
+}
+
+}  // namespace tdmps

@@ -1,0 +1,211 @@
+// Time steps built from the fit: RK4 (Eqs. (k1-k4), (rk_add)) and Krylov (Eqs. (kry_non),
+// (kry_orth), (krylov_evo)).  The m x m Krylov algebra runs on the host in FP64.
+#include <cmath>
+#include <complex>
+#include <memory>
+
+#include "drivers.h"
+
+namespace tdmps {
+
+using zd = std::complex<double>;
+
+namespace {
+
+// Cyclic Jacobi for a Hermitian n x n matrix (row-major): A = Q diag(w) Q^H.
+void herm_eig(int n, std::vector<zd> A, std::vector<double>& w, std::vector<zd>& Q) {
+  Q.assign((size_t)n * n, zd(0));
+  for (int i = 0; i < n; ++i) Q[i * n + i] = 1.0;
+  auto at = [&](int r, int c) -> zd& { return A[(size_t)r * n + c]; };
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0, tot = 0;
+    for (int r = 0; r < n; ++r)
+      for (int c = 0; c < n; ++c) (r == c ? tot : off) += std::norm(at(r, c));
+    if (off <= 1e-30 * (tot + off) || off == 0.0) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        zd g = at(p, q);
+        double ag = std::abs(g);
+        if (ag == 0.0) continue;
+        double a = at(p, p).real(), b = at(q, q).real();
+        zd ph = g / ag;  // e^{i phi}
+        double zeta = (b - a) / (2 * ag);
+        double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1 + zeta * zeta));
+        double c = 1 / std::sqrt(1 + t * t), s = c * t;
+        // J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] on (p, q)
+        zd em = std::conj(ph);
+        for (int k = 0; k < n; ++k) {  // columns: A <- A J
+          zd x = at(k, p), y = at(k, q);
+          at(k, p) = c * x - s * em * y;
+          at(k, q) = s * x + c * em * y;
+        }
+        for (int k = 0; k < n; ++k) {  // rows: A <- J^H A
+          zd x = at(p, k), y = at(q, k);
+          at(p, k) = c * x - s * ph * y;
+          at(q, k) = s * x + c * ph * y;
+        }
+        for (int k = 0; k < n; ++k) {
+          zd x = Q[(size_t)k * n + p], y = Q[(size_t)k * n + q];
+          Q[(size_t)k * n + p] = c * x - s * em * y;
+          Q[(size_t)k * n + q] = s * x + c * em * y;
+        }
+      }
+  }
+  w.resize(n);
+  for (int i = 0; i < n; ++i) w[i] = at(i, i).real();
+}
+
+}  // namespace
+
+std::vector<zd> krylov_coefficients(int m, const std::vector<zd>& Nin, const std::vector<zd>& Hin, double dt,
+                                    bool orthogonal) {
+  std::vector<zd> N(Nin), H(Hin);
+  for (int r = 0; r < m; ++r)
+    for (int c = r; c < m; ++c) {
+      zd a = 0.5 * (N[r * m + c] + std::conj(N[c * m + r]));
+      N[r * m + c] = a;
+      N[c * m + r] = std::conj(a);
+      zd b = 0.5 * (H[r * m + c] + std::conj(H[c * m + r]));
+      H[r * m + c] = b;
+      H[c * m + r] = std::conj(b);
+    }
+  std::vector<double> nw;
+  std::vector<zd> Q;
+  herm_eig(m, N, nw, Q);
+  double nmax = 0;
+  for (double x : nw) nmax = std::max(nmax, x);
+  TDMPS_REQUIRE(nmax > 0, TDMPS_ERR_SINGULAR, "Krylov overlap matrix is zero");
+  std::vector<int> keep;
+  for (int i = 0; i < m; ++i) {
+    if (nw[i] > 1e-12 * nmax)
+      keep.push_back(i);
+    else
+      TDMPS_REQUIRE(!orthogonal, TDMPS_ERR_SINGULAR, "Krylov overlap matrix is not positive definite");
+  }
+  int r = (int)keep.size();
+  // X = Q_keep diag(n^-1/2): X^H N X = 1
+  std::vector<zd> X((size_t)m * r);
+  for (int a = 0; a < m; ++a)
+    for (int j = 0; j < r; ++j) X[a * r + j] = Q[a * m + keep[j]] / std::sqrt(nw[keep[j]]);
+  std::vector<zd> Hp((size_t)r * r, zd(0));
+  for (int i = 0; i < r; ++i)
+    for (int j = 0; j < r; ++j) {
+      zd s = 0;
+      for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) s += std::conj(X[a * r + i]) * H[a * m + b] * X[b * r + j];
+      Hp[i * r + j] = s;
+    }
+  std::vector<double> lam;
+  std::vector<zd> Y;
+  herm_eig(r, Hp, lam, Y);
+  // V = X Y;  c = V exp(-i dt lam) V^H N e0
+  std::vector<zd> V((size_t)m * r, zd(0));
+  for (int a = 0; a < m; ++a)
+    for (int j = 0; j < r; ++j) {
+      zd s = 0;
+      for (int i = 0; i < r; ++i) s += X[a * r + i] * Y[i * r + j];
+      V[a * r + j] = s;
+    }
+  std::vector<zd> Ne0(m);
+  for (int a = 0; a < m; ++a) Ne0[a] = N[a * m + 0];
+  std::vector<zd> y(r);
+  for (int j = 0; j < r; ++j) {
+    zd s = 0;
+    for (int a = 0; a < m; ++a) s += std::conj(V[a * r + j]) * Ne0[a];
+    y[j] = s * std::exp(zd(0, -dt * lam[j]));
+  }
+  std::vector<zd> c(m);
+  for (int a = 0; a < m; ++a) {
+    zd s = 0;
+    for (int j = 0; j < r; ++j) s += V[a * r + j] * y[j];
+    c[a] = s;
+  }
+  return c;
+}
+
+Mps* rk4_step(Contractor& C, const MpoHost* Ht, const MpoHost* Hm, const MpoHost* Ht1, const Mps* psi, double dt,
+              const tdmps_fit_params& prm, FitOut* info) {
+  cplx a{0.0, -dt};
+  FitOut fo, acc;
+  auto track = [&](const FitOut& f) {
+    acc.sweeps = std::max(acc.sweeps, f.sweeps);
+    acc.disc_max = std::max(acc.disc_max, f.disc_max);
+    acc.disc_sum += f.disc_sum;
+  };
+  std::unique_ptr<Mps> k1(fit(C, Ht, a, psi, {}, prm, &fo));
+  track(fo);
+  std::unique_ptr<Mps> u2(fit(C, nullptr, a, nullptr, {{cplx{1, 0}, psi}, {cplx{0.5, 0}, k1.get()}}, prm, &fo));
+  track(fo);
+  std::unique_ptr<Mps> k2(fit(C, Hm, a, u2.get(), {}, prm, &fo));
+  track(fo);
+  u2.reset();
+  std::unique_ptr<Mps> u3(fit(C, nullptr, a, nullptr, {{cplx{1, 0}, psi}, {cplx{0.5, 0}, k2.get()}}, prm, &fo));
+  track(fo);
+  std::unique_ptr<Mps> k3(fit(C, Hm, a, u3.get(), {}, prm, &fo));
+  track(fo);
+  u3.reset();
+  std::unique_ptr<Mps> u4(fit(C, nullptr, a, nullptr, {{cplx{1, 0}, psi}, {cplx{1, 0}, k3.get()}}, prm, &fo));
+  track(fo);
+  std::unique_ptr<Mps> k4(fit(C, Ht1, a, u4.get(), {}, prm, &fo));
+  track(fo);
+  u4.reset();
+  Mps* out = fit(C, nullptr, a, nullptr,
+                 {{cplx{1, 0}, psi},
+                  {cplx{1.0 / 6, 0}, k1.get()},
+                  {cplx{1.0 / 3, 0}, k2.get()},
+                  {cplx{1.0 / 3, 0}, k3.get()},
+                  {cplx{1.0 / 6, 0}, k4.get()}},
+                 prm, &fo);
+  track(fo);
+  acc.norm2 = fo.norm2;
+  if (info) *info = acc;
+  return out;
+}
+
+Mps* krylov_step(Contractor& C, const MpoHost* H, const Mps* psi, double dt, int m, bool orthogonal,
+                 const tdmps_fit_params& prm, std::vector<zd>* Nout, std::vector<zd>* Hout) {
+  TDMPS_REQUIRE(m >= 2 && m <= 64, TDMPS_ERR_ARG, "Krylov dimension must be in [2, 64]");
+  auto z = [](cplx c) { return zd(c.x, c.y); };
+  double n0 = overlap(C, psi, psi).x;
+  TDMPS_REQUIRE(n0 > 0 && std::isfinite(n0), TDMPS_ERR_NUMERIC, "state has zero or non-finite norm");
+  double s0 = std::sqrt(n0);
+  std::vector<std::unique_ptr<Mps>> phi;
+  phi.emplace_back(mps_clone(psi));
+  scale_mps(C.ctx, phi[0].get(), cplx{1.0 / s0, 0.0});
+  std::vector<zd> N((size_t)m * m, zd(0)), Hm((size_t)m * m, zd(0));
+  N[0] = z(overlap(C, phi[0].get(), phi[0].get()));
+  for (int k = 0; k < m - 1; ++k) {
+    for (int j = 0; j <= k; ++j) {
+      Hm[j * m + k] = z(sandwich(C, *H, phi[j].get(), phi[k].get()));
+      Hm[k * m + j] = std::conj(Hm[j * m + k]);
+    }
+    std::vector<FitTerm> terms;
+    if (orthogonal)
+      for (int j = 0; j <= k; ++j) {
+        zd b = -Hm[j * m + k] / N[j * m + j];
+        terms.push_back({cplx{b.real(), b.imag()}, phi[j].get()});
+      }
+    std::unique_ptr<Mps> nxt(fit(C, H, cplx{1, 0}, phi[k].get(), terms, prm, nullptr));
+    double nn = overlap(C, nxt.get(), nxt.get()).x;
+    TDMPS_REQUIRE(nn > 0 && std::isfinite(nn), TDMPS_ERR_SINGULAR, "Krylov vector vanished");
+    scale_mps(C.ctx, nxt.get(), cplx{1.0 / std::sqrt(nn), 0.0});
+    phi.push_back(std::move(nxt));
+    for (int j = 0; j <= k + 1; ++j) {
+      N[j * m + k + 1] = z(overlap(C, phi[j].get(), phi[k + 1].get()));
+      N[(k + 1) * m + j] = std::conj(N[j * m + k + 1]);
+    }
+  }
+  for (int j = 0; j < m; ++j) {
+    Hm[j * m + m - 1] = z(sandwich(C, *H, phi[j].get(), phi[m - 1].get()));
+    Hm[(m - 1) * m + j] = std::conj(Hm[j * m + m - 1]);
+  }
+  auto c = krylov_coefficients(m, N, Hm, dt, orthogonal);
+  std::vector<FitTerm> terms;
+  for (int k = 0; k < m; ++k) terms.push_back({cplx{s0 * c[k].real(), s0 * c[k].imag()}, phi[k].get()});
+  Mps* out = fit(C, nullptr, cplx{1, 0}, nullptr, terms, prm, nullptr);
+  if (Nout) *Nout = N;
+  if (Hout) *Hout = Hm;
+  return out;
+}
+
+}  // namespace tdmps

@@ -1,0 +1,295 @@
+// Host-side data structures of the block-sparse MPS engine and its internal API.
+#pragma once
+
+#include <array>
+#include <functional>
+#include <memory>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+#include "mpo.h"
+
+struct tdmps_ctx_s;
+
+namespace tdmps {
+
+const char* last_error_cstr();
+
+// Runs f, converting exceptions to a status code and the thread-local message.
+template <class F>
+tdmps_status guard(F&& f) {
+  try {
+    f();
+    return TDMPS_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return TDMPS_ERR_OOM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return TDMPS_ERR_ARG;
+  }
+}
+
+// ---------------------------------------------------------------- device buffers
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t b);
+  ~DevBuf();
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
+  void release();
+  cplx* c() const { return (cplx*)p; }
+};
+
+// ---------------------------------------------------------------- bonds and layouts
+struct Bond {
+  std::vector<Charge> q;  // sorted ascending
+  std::vector<int> dim;
+  int find(Charge c) const;
+  int nsec() const { return (int)q.size(); }
+  int total() const {
+    int t = 0;
+    for (int d : dim) t += d;
+    return t;
+  }
+};
+
+// Site tensor A[a, n, b]: per left sector a row-major panel D_a x width whose columns are
+// the blocks n = 0..3 (right sector rs[a][n], column offset col[a][n]).
+struct SiteLayout {
+  std::vector<int64_t> panel_off;
+  std::vector<int> width;
+  std::vector<std::array<int, 4>> rs, col;
+  int64_t size = 0;
+  void build(const Bond& l, const Bond& r);
+};
+
+// Two-site tensor theta[a, n1, n2, b] with combined index n = 4 n1 + n2.
+struct TwoLayout {
+  std::vector<int64_t> panel_off;
+  std::vector<int> width;
+  std::vector<std::array<int, 16>> rs, col;
+  int64_t size = 0;
+  void build(const Bond& l, const Bond& r);
+};
+
+inline Charge pair_charge(int n) { return local_charge(n >> 2) + local_charge(n & 3); }
+
+}  // namespace tdmps
+
+struct tdmps_ctx_s {
+  int device = 0;
+  void* stream = nullptr;
+  bool own_stream = false;
+  void* ev[2] = {nullptr, nullptr};
+  double counters[8] = {0};
+  bool timing = false;
+};
+
+struct tdmps_mps_s {
+  tdmps_ctx ctx = nullptr;
+  int L = 0;
+  tdmps::Charge total;
+  std::vector<tdmps::Bond> bond;        // L + 1
+  std::vector<tdmps::SiteLayout> lay;   // L
+  std::vector<tdmps::DevBuf> site;      // L
+};
+
+struct tdmps_mpo_s {
+  tdmps_ctx ctx = nullptr;
+  tdmps::MpoHost host;
+};
+
+namespace tdmps {
+
+using Ctx = tdmps_ctx_s;
+using Mps = tdmps_mps_s;
+
+// ---------------------------------------------------------------- environment-like data
+// Groups of n "channels" with common charge q.  For every ket sector k whose bra sector
+// b (q_b = q_k + q) exists, a stack [n][D_b][D_k] (row-major blocks) is stored.
+struct StackGroup {
+  Charge q;
+  int n = 0;
+  std::vector<int> bra_of;   // per ket sector
+  std::vector<int> ket_of;   // per bra sector
+  std::vector<int64_t> off;  // per ket sector, -1 if absent
+};
+
+struct Blocks {
+  Bond bra, ket;
+  std::vector<StackGroup> grp;
+  DevBuf data;
+  int64_t size = 0;
+  void layout(const Bond& b, const Bond& k, const std::vector<std::pair<Charge, int>>& groups);
+  cplx* stack(int g, int ks) const { return grp[g].off[ks] < 0 ? nullptr : data.c() + grp[g].off[ks]; }
+};
+
+// Environment of an MPO cut: one group per channel class of the cut.
+struct Env {
+  int cut = 0;
+  Blocks b;
+};
+
+// Operator of a middle channel for one local matrix unit (s, sp): coef * source[grp][idx].
+struct OpRef {
+  const Blocks* src = nullptr;
+  int grp = 0, idx = 0;
+  double coef = 0;
+};
+
+struct ChanOps {
+  std::vector<int> pat;  // local matrix unit 4*s + sp
+  std::vector<OpRef> ref;
+};
+
+// Environment operators combined with one site tensor of the MPO, per channel of the
+// middle cut and local matrix unit (premix).  Single-source entries alias the
+// environment; multi-source ones are linear combinations computed on the device.
+struct SideOps {
+  int cut = 0;  // middle cut
+  const Env* env = nullptr;
+  std::vector<ChanOps> ch;
+  std::unique_ptr<Blocks> mix;
+};
+
+// ---------------------------------------------------------------- GEMM plans
+struct GemmPlan {
+  std::vector<GemmTask> tasks;
+  std::vector<GemmSeg> segs;
+  double flops = 0;  // executed flops (8 per complex multiply-add)
+  int begin_task(cplx* C, int64_t bsC, int ldc, int m, int n, int nbatch, bool accum);
+  void add_seg(const cplx* A, int64_t bsA, int64_t rsA, int lda, int opA, const cplx* B, int64_t bsB, int64_t rsB,
+               int ldb, int opB, int k, int nred, cplx alpha);
+  // device copies of the task lists (finalize) and asynchronous launch
+  DevBuf dsegs, dtasks[2];
+  int ntask[2] = {0, 0};
+  int64_t ntiles[2] = {0, 0};
+  bool final_ = false;
+  void finalize(Ctx* ctx);
+  void launch(Ctx* ctx, int precision);
+  void run(Ctx* ctx, int precision);  // finalize + launch + synchronise
+  bool empty() const { return tasks.empty(); }
+};
+
+struct CopyPlan {
+  std::vector<CopyTask> tasks;
+  void add(const cplx* src, int64_t src_rs, int64_t src_cs, cplx* dst, int dst_ld, int rows, int cols, int flags,
+           const int32_t* ridx = nullptr, const int32_t* cidx = nullptr, const double* rs = nullptr,
+           const double* cs = nullptr);
+  void run(Ctx* ctx);
+};
+
+// Host vectors copied to the device for the lifetime of an operation.
+struct Staging {
+  std::vector<DevBuf> bufs;
+  template <class T>
+  const T* put(Ctx* ctx, const std::vector<T>& v) {
+    if (v.empty()) return nullptr;
+    bufs.emplace_back(v.size() * sizeof(T));
+    dev_h2d(bufs.back().p, v.data(), v.size() * sizeof(T), ctx->stream);
+    return (const T*)bufs.back().p;
+  }
+};
+
+// ---------------------------------------------------------------- engine API
+struct Contractor {
+  Ctx* ctx;
+  int precision = TDMPS_FP64;
+  int batched = 1;
+  double heff_flops = 0, env_flops = 0, mix_flops = 0;
+  double heff_alg_flops = 0;
+};
+
+Mps* mps_new(Ctx* ctx, int L, const std::vector<Bond>& bonds);
+Mps* mps_clone(const Mps* m);
+void mps_from_det(Mps* m, const uint8_t* occ);
+MpoHost identity_mpo(int L);
+
+Env env_left_boundary(Ctx* ctx, const Bond& bra0, const Bond& ket0);
+Env env_right_boundary(Ctx* ctx, const Bond& braL, const Bond& ketL, int L);
+
+SideOps premix_left(Contractor& C, const Env& L, const MpoHost& W, int site);
+SideOps premix_right(Contractor& C, const Env& R, const MpoHost& W, int site);
+
+Env env_left_update(Contractor& C, const SideOps& ops, const Mps* bra, const cplx* bra_site, const SiteLayout& bl,
+                    const Bond& bra_l, const Bond& bra_r, const cplx* ket_site, const SiteLayout& kl,
+                    const Bond& ket_l, const Bond& ket_r, const MpoHost& W);
+Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, const SiteLayout& bl, const Bond& bra_l,
+                     const Bond& bra_r, const cplx* ket_site, const SiteLayout& kl, const Bond& ket_l,
+                     const Bond& ket_r, const MpoHost& W);
+
+// theta_out (bra two-site layout) (+)= alpha * H_eff theta_in (ket two-site layout)
+struct HeffPlan {
+  GemmPlan p1, p2;
+  DevBuf T;
+  cplx* out = nullptr;
+  int64_t out_size = 0;
+  bool accumulate = false;
+  double alg_flops = 0;
+  void launch(Ctx* ctx, int precision);
+};
+std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const SideOps& rops, const cplx* theta_in,
+                                    const TwoLayout& kl, const Bond& ket_l, const Bond& ket_r, cplx* theta_out,
+                                    const TwoLayout& bl, const Bond& bra_l, const Bond& bra_r, cplx alpha,
+                                    bool accumulate);
+void heff_apply(Contractor& C, const SideOps& lops, const SideOps& rops, const cplx* theta_in, const TwoLayout& kl,
+                const Bond& ket_l, const Bond& ket_r, cplx* theta_out, const TwoLayout& bl, const Bond& bra_l,
+                const Bond& bra_r, cplx alpha, bool accumulate, double* alg_flops);
+
+// theta (two-site) = A_i A_{i+1}
+void form_theta(Contractor& C, const Mps* m, int i, cplx* theta, const TwoLayout& tl);
+
+// full left sweep of environments: <bra|O|ket>
+cplx sandwich(Contractor& C, const MpoHost& O, const Mps* bra, const Mps* ket);
+
+struct TruncResult {
+  Bond mid;
+  double discarded = 0, norm2 = 0;
+  int kept = 0;
+};
+// SVD of a two-site tensor (bra layout over bonds l, r), truncation to Dmax, and the
+// split into the two site tensors.  move_right: A_i = U, A_{i+1} = S V^H; else A_i = U S,
+// A_{i+1} = V^H.  The new site buffers and layouts are written into m at i, i+1.
+TruncResult split_theta(Contractor& C, const cplx* theta, const TwoLayout& tl, Mps* m, int i, int Dmax, double cutoff,
+                        bool move_right);
+void right_canonicalize(Contractor& C, Mps* m, double cutoff);
+
+struct FitTerm {
+  cplx beta;
+  const Mps* phi;
+};
+struct FitOut {
+  int sweeps = 0;
+  double disc_max = 0, disc_sum = 0, norm2 = 0;
+};
+// out ~ alpha * H psi + sum_j beta_j phi_j  (H may be null: compression only)
+Mps* fit(Contractor& C, const MpoHost* H, cplx alpha, const Mps* psi, const std::vector<FitTerm>& terms,
+         const tdmps_fit_params& prm, FitOut* info);
+
+void scale_mps(Ctx* ctx, Mps* m, cplx alpha);
+cplx overlap(Contractor& C, const Mps* a, const Mps* b);
+
+}  // namespace tdmps

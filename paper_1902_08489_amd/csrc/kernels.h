@@ -1,0 +1,91 @@
+// Interface between the host planner and the device: runtime calls and kernel launchers.
+// Every HIP call of the library sits behind these functions (device.hip, gemm.hip,
+// misc.hip); the planner and the drivers only see plain pointers and task lists.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace tdmps {
+
+struct cplx {
+  double x, y;
+};
+
+// ---------------------------------------------------------------- grouped complex GEMM
+// One task writes (or accumulates into) nbatch independent m x n outputs
+//   C_b = [C_b +] sum_seg alpha_seg * sum_{r < nred} op(A_seg + b*bsA + r*rsA) op(B_seg + b*bsB + r*rsB)
+// with op in {N, T, C (conjugate transpose), J (conjugate)}; op(A) is m x k, op(B) k x n,
+// all row-major with leading dimensions lda, ldb, ldc (in complex elements).
+enum { OP_N = 0, OP_T = 1, OP_C = 2, OP_J = 3 };
+enum { GEMM_ACCUM = 1 };
+
+struct GemmTask {
+  cplx* C;
+  int64_t bsC;
+  int32_t ldc, m, n, nbatch;
+  int32_t seg0, nseg;
+  int32_t tiles_m, tiles_n, flags;
+  int64_t tile_base;  // exclusive prefix of nbatch*tiles_m*tiles_n over previous tasks
+};
+
+struct GemmSeg {
+  const cplx* A;
+  const cplx* B;
+  int64_t bsA, bsB, rsA, rsB;
+  int32_t nred, k, lda, ldb, opA, opB;
+  cplx alpha;
+};
+
+// ---------------------------------------------------------------- strided block copies
+// dst[r*dst_ld + c] (+)= op(src[(ridx?ridx[r]:r)*src_rs + (cidx?cidx[c]:c)*src_cs]) * rs[r] * cs[c]
+struct CopyTask {
+  const cplx* src;
+  cplx* dst;
+  int64_t src_rs, src_cs;
+  const int32_t* ridx;
+  const int32_t* cidx;
+  const double* rscale;
+  const double* cscale;
+  int32_t rows, cols, dst_ld, flags;  // flags: 1 = conjugate source, 2 = accumulate
+};
+
+// ---------------------------------------------------------------- one-sided Jacobi SVD
+// Matrix j holds k vectors of length ell (column-major G, column stride ell) and the k x k
+// accumulated rotation V (column-major, column stride k).
+struct SvdMat {
+  cplx* G;
+  cplx* V;
+  int32_t ell, k, kpad, pair_base;  // pair_base: exclusive prefix of kpad/2 over matrices
+  double thr;                       // pairs with |g_p^H g_q| <= thr max(|g_p|, |g_q|) are orthogonal
+};
+
+// runtime
+void dev_set_device(int device);
+void* dev_alloc(size_t bytes);  // returns nullptr when out of memory
+void dev_free(void* p);
+void dev_h2d(void* dst, const void* src, size_t bytes, void* stream);
+void dev_d2h(void* dst, const void* src, size_t bytes, void* stream);  // host data valid on return
+void dev_d2d(void* dst, const void* src, size_t bytes, void* stream);
+void dev_zero(void* dst, size_t bytes, void* stream);  // fill kernel (no memset nodes)
+void dev_sync(void* stream);
+void* dev_stream_create();
+void dev_stream_destroy(void* s);
+void* dev_event_create();
+void dev_event_destroy(void* e);
+void dev_event_record(void* e, void* stream);
+float dev_event_elapsed_ms(void* a, void* b);  // synchronises on b
+
+// launchers (all asynchronous on `stream`)
+void launch_gemm(const GemmTask* tasks, const GemmSeg* segs, int ntasks, int64_t total_tiles, int cfg, int precision,
+                 void* stream);
+int gemm_tile_m(int cfg);
+int gemm_tile_n(int cfg);
+void launch_copy(const CopyTask* tasks, int ntasks, void* stream);
+void launch_svd_init(const SvdMat* mats, int nmats, void* stream);  // V = identity
+void launch_svd_round(const SvdMat* mats, int nmats, int64_t total_pairs, int round, double tol, int32_t* rot_counter,
+                      void* stream);
+void launch_svd_norms(const SvdMat* mats, int nmats, int max_k, double* sigma_out, void* stream);
+void launch_scale(cplx* x, int64_t n, cplx alpha, void* stream);
+
+}  // namespace tdmps

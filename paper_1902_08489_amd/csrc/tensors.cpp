@@ -1,0 +1,300 @@
+// Block-sparse layouts, device buffers, task plans and basic state constructors.
+#include <algorithm>
+#include <cstring>
+
+#include "engine.h"
+
+namespace tdmps {
+
+// ---------------------------------------------------------------- device buffers
+DevBuf::DevBuf(size_t b) : bytes(b) {
+  if (b == 0) return;
+  p = dev_alloc(b);
+  TDMPS_REQUIRE(p != nullptr, TDMPS_ERR_OOM, "device allocation of " + std::to_string(b) + " bytes failed");
+}
+DevBuf::~DevBuf() { release(); }
+void DevBuf::release() {
+  if (p) dev_free(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+// ---------------------------------------------------------------- bonds and layouts
+int Bond::find(Charge c) const {
+  auto it = std::lower_bound(q.begin(), q.end(), c);
+  if (it == q.end() || *it != c) return -1;
+  return (int)(it - q.begin());
+}
+
+void SiteLayout::build(const Bond& l, const Bond& r) {
+  int n = l.nsec();
+  panel_off.assign(n, 0);
+  width.assign(n, 0);
+  rs.assign(n, {-1, -1, -1, -1});
+  col.assign(n, {0, 0, 0, 0});
+  size = 0;
+  for (int a = 0; a < n; ++a) {
+    int w = 0;
+    for (int s = 0; s < 4; ++s) {
+      int b = r.find(l.q[a] + local_charge(s));
+      rs[a][s] = b;
+      if (b >= 0) {
+        col[a][s] = w;
+        w += r.dim[b];
+      }
+    }
+    width[a] = w;
+    panel_off[a] = size;
+    size += (int64_t)l.dim[a] * w;
+  }
+}
+
+void TwoLayout::build(const Bond& l, const Bond& r) {
+  int n = l.nsec();
+  panel_off.assign(n, 0);
+  width.assign(n, 0);
+  rs.assign(n, {});
+  col.assign(n, {});
+  size = 0;
+  for (int a = 0; a < n; ++a) {
+    int w = 0;
+    for (int s = 0; s < 16; ++s) {
+      int b = r.find(l.q[a] + pair_charge(s));
+      rs[a][s] = b;
+      col[a][s] = 0;
+      if (b >= 0) {
+        col[a][s] = w;
+        w += r.dim[b];
+      }
+    }
+    width[a] = w;
+    panel_off[a] = size;
+    size += (int64_t)l.dim[a] * w;
+  }
+}
+
+void Blocks::layout(const Bond& b, const Bond& k, const std::vector<std::pair<Charge, int>>& groups) {
+  bra = b;
+  ket = k;
+  grp.clear();
+  size = 0;
+  for (auto& g : groups) {
+    StackGroup sg;
+    sg.q = g.first;
+    sg.n = g.second;
+    sg.bra_of.assign(k.nsec(), -1);
+    sg.ket_of.assign(b.nsec(), -1);
+    sg.off.assign(k.nsec(), -1);
+    for (int ks = 0; ks < k.nsec(); ++ks) {
+      int bs = b.find(k.q[ks] + g.first);
+      if (bs < 0) continue;
+      sg.bra_of[ks] = bs;
+      sg.ket_of[bs] = ks;
+      sg.off[ks] = size;
+      size += (int64_t)g.second * b.dim[bs] * k.dim[ks];
+    }
+    grp.push_back(std::move(sg));
+  }
+}
+
+// ---------------------------------------------------------------- plans
+int GemmPlan::begin_task(cplx* C, int64_t bsC, int ldc, int m, int n, int nbatch, bool accum) {
+  GemmTask t;
+  t.C = C;
+  t.bsC = bsC;
+  t.ldc = ldc;
+  t.m = m;
+  t.n = n;
+  t.nbatch = nbatch;
+  t.seg0 = (int32_t)segs.size();
+  t.nseg = 0;
+  t.tiles_m = t.tiles_n = 0;
+  t.flags = accum ? GEMM_ACCUM : 0;
+  t.tile_base = 0;
+  tasks.push_back(t);
+  return (int)tasks.size() - 1;
+}
+
+void GemmPlan::add_seg(const cplx* A, int64_t bsA, int64_t rsA, int lda, int opA, const cplx* B, int64_t bsB,
+                       int64_t rsB, int ldb, int opB, int k, int nred, cplx alpha) {
+  GemmSeg s;
+  s.A = A;
+  s.B = B;
+  s.bsA = bsA;
+  s.bsB = bsB;
+  s.rsA = rsA;
+  s.rsB = rsB;
+  s.nred = nred;
+  s.k = k;
+  s.lda = lda;
+  s.ldb = ldb;
+  s.opA = opA;
+  s.opB = opB;
+  s.alpha = alpha;
+  segs.push_back(s);
+  GemmTask& t = tasks.back();
+  t.nseg++;
+  flops += 8.0 * t.m * (double)t.n * k * nred * t.nbatch;
+}
+
+void GemmPlan::finalize(Ctx* ctx) {
+  if (final_) return;
+  final_ = true;
+  // drop tasks without work that do not need to overwrite their output
+  std::vector<GemmTask> keep;
+  keep.reserve(tasks.size());
+  for (auto& t : tasks)
+    if (t.m > 0 && t.n > 0 && t.nbatch > 0 && (t.nseg > 0 || !(t.flags & GEMM_ACCUM))) keep.push_back(t);
+  if (keep.empty()) return;
+  if (!segs.empty()) {
+    dsegs = DevBuf(segs.size() * sizeof(GemmSeg));
+    dev_h2d(dsegs.p, segs.data(), segs.size() * sizeof(GemmSeg), ctx->stream);
+  }
+  // tile configuration per task: small outputs take the small tile
+  for (int cfg = 0; cfg < 2; ++cfg) {
+    std::vector<GemmTask> sel;
+    int64_t base = 0;
+    int tm = gemm_tile_m(cfg), tn = gemm_tile_n(cfg);
+    for (auto t : keep) {
+      bool big = (t.m > 40 && t.n > 40);
+      if ((cfg == 0) != big) continue;
+      t.tiles_m = (t.m + tm - 1) / tm;
+      t.tiles_n = (t.n + tn - 1) / tn;
+      t.tile_base = base;
+      base += (int64_t)t.nbatch * t.tiles_m * t.tiles_n;
+      sel.push_back(t);
+    }
+    ntask[cfg] = (int)sel.size();
+    ntiles[cfg] = base;
+    if (sel.empty()) continue;
+    dtasks[cfg] = DevBuf(sel.size() * sizeof(GemmTask));
+    dev_h2d(dtasks[cfg].p, sel.data(), sel.size() * sizeof(GemmTask), ctx->stream);
+  }
+}
+
+void GemmPlan::launch(Ctx* ctx, int precision) {
+  for (int cfg = 0; cfg < 2; ++cfg)
+    if (ntask[cfg] > 0)
+      launch_gemm((const GemmTask*)dtasks[cfg].p, (const GemmSeg*)dsegs.p, ntask[cfg], ntiles[cfg], cfg, precision,
+                  ctx->stream);
+}
+
+void GemmPlan::run(Ctx* ctx, int precision) {
+  finalize(ctx);
+  launch(ctx, precision);
+  dev_sync(ctx->stream);
+}
+
+void CopyPlan::add(const cplx* src, int64_t src_rs, int64_t src_cs, cplx* dst, int dst_ld, int rows, int cols, int flags,
+                   const int32_t* ridx, const int32_t* cidx, const double* rs, const double* cs) {
+  if (rows <= 0 || cols <= 0) return;
+  CopyTask t;
+  t.src = src;
+  t.dst = dst;
+  t.src_rs = src_rs;
+  t.src_cs = src_cs;
+  t.ridx = ridx;
+  t.cidx = cidx;
+  t.rscale = rs;
+  t.cscale = cs;
+  t.rows = rows;
+  t.cols = cols;
+  t.dst_ld = dst_ld;
+  t.flags = flags;
+  tasks.push_back(t);
+}
+
+void CopyPlan::run(Ctx* ctx) {
+  if (tasks.empty()) return;
+  Staging st;
+  const CopyTask* d = st.put(ctx, tasks);
+  launch_copy(d, (int)tasks.size(), ctx->stream);
+  dev_sync(ctx->stream);
+}
+
+// ---------------------------------------------------------------- states
+Mps* mps_new(Ctx* ctx, int L, const std::vector<Bond>& bonds) {
+  TDMPS_REQUIRE((int)bonds.size() == L + 1, TDMPS_ERR_ARG, "need L+1 bonds");
+  auto* m = new Mps();
+  try {
+    m->ctx = ctx;
+    m->L = L;
+    m->bond = bonds;
+    TDMPS_REQUIRE(bonds[0].nsec() == 1 && bonds[0].q[0] == Charge(0, 0) && bonds[0].dim[0] == 1, TDMPS_ERR_ARG,
+                  "bond 0 must be the single sector (0,0) of dimension 1");
+    TDMPS_REQUIRE(bonds[L].nsec() == 1 && bonds[L].dim[0] == 1, TDMPS_ERR_ARG,
+                  "bond L must be a single sector of dimension 1");
+    m->total = bonds[L].q[0];
+    m->lay.resize(L);
+    m->site.resize(L);
+    for (int i = 0; i < L; ++i) {
+      m->lay[i].build(bonds[i], bonds[i + 1]);
+      m->site[i] = DevBuf(m->lay[i].size * sizeof(cplx));
+      if (m->lay[i].size) dev_zero(m->site[i].p, m->site[i].bytes, ctx->stream);
+    }
+  } catch (...) {
+    delete m;
+    throw;
+  }
+  return m;
+}
+
+Mps* mps_clone(const Mps* src) {
+  auto* m = new Mps();
+  try {
+    m->ctx = src->ctx;
+    m->L = src->L;
+    m->total = src->total;
+    m->bond = src->bond;
+    m->lay = src->lay;
+    m->site.resize(src->L);
+    for (int i = 0; i < src->L; ++i) {
+      m->site[i] = DevBuf(src->site[i].bytes);
+      if (src->site[i].bytes) dev_d2d(m->site[i].p, src->site[i].p, src->site[i].bytes, src->ctx->stream);
+    }
+  } catch (...) {
+    delete m;
+    throw;
+  }
+  return m;
+}
+
+void mps_from_det(Mps* m, const uint8_t* occ) {
+  std::vector<cplx> one(1, cplx{1.0, 0.0});
+  for (int i = 0; i < m->L; ++i) {
+    TDMPS_REQUIRE(m->lay[i].size == 1, TDMPS_ERR_ARG, "determinant layout");
+    dev_h2d(m->site[i].p, one.data(), sizeof(cplx), m->ctx->stream);
+  }
+  dev_sync(m->ctx->stream);
+}
+
+MpoHost identity_mpo(int L) {
+  MpoHost M;
+  M.L = L;
+  M.cut.resize(L + 1);
+  for (auto& c : M.cut) {
+    c.key = {0};
+    c.q = {Charge(0, 0)};
+    c.parity = {0};
+    c.cls_q = {Charge(0, 0)};
+    c.cls_start = {0};
+    c.cls_count = {1};
+    c.cls_of = {0};
+  }
+  M.W.resize(L);
+  M.c_fixed.resize(L);
+  for (int p = 0; p < L; ++p)
+    for (int s = 0; s < 4; ++s) {
+      M.W[p].push_back({0, 0, (int8_t)s, (int8_t)s, 1.0});
+      M.c_fixed[p].push_back(1.0);
+    }
+  M.h.assign((size_t)L * L, 0.0);
+  return M;
+}
+
+void scale_mps(Ctx* ctx, Mps* m, cplx alpha) {
+  if (m->lay[0].size) launch_scale(m->site[0].c(), m->lay[0].size, alpha, ctx->stream);
+  dev_sync(ctx->stream);
+}
+
+}  // namespace tdmps

@@ -204,3 +204,104 @@ def det_basis_sets(L, Nu, Nd, dims_per_bond, ref_occ, seed, left_upto, right_fro
 
 def local_states():
     return list(product(range(2), range(2)))
+
+
+def _panel_layout(left, right):
+    """Panel layout of a site tensor given ascending sector lists [(q, dim)] of its bonds:
+    returns (offset per left sector, width per left sector, {(s, n): (t, col)})."""
+    rindex = {q: (t, d) for t, (q, d) in enumerate(right)}
+    offs, widths, blocks = [], [], {}
+    off = 0
+    for s, (q, d) in enumerate(left):
+        w = 0
+        for n in range(4):
+            nq = (q[0] + LOCAL_CHARGE[n][0], q[1] + LOCAL_CHARGE[n][1])
+            if nq in rindex:
+                t, dt = rindex[nq]
+                blocks[(s, n)] = (t, w)
+                w += dt
+        offs.append(off)
+        widths.append(w)
+        off += d * w
+    return offs, widths, blocks, off
+
+
+def det_basis_state(L, Nu, Nd, D, sigma=1.0, seed=0, centre=None):
+    """A block-sparse state whose bonds left of `centre` and right of `centre + 2` are
+    orthonormal determinant bases (0/1 selection tensors), in the library's panel layout.
+
+    With such a state the two-site effective Hamiltonian at bond (centre, centre+1) is the
+    FCI Hamiltonian restricted to the determinants  S[a] (x) n1 (x) n2 (x) T[b].
+    Returns (bonds, data, S_c, T_c2) where bonds are ascending [(n_up, n_dn, dim)] lists,
+    data the concatenated complex site tensors, S_c / T_c2 dicts charge -> determinant list.
+    """
+    c = L // 2 - 1 if centre is None else centre
+    alloc = sector_allocation(L, Nu, Nd, D, sigma)
+    ref = determinant(L, Nu, Nd, seed + 7)
+    S, T = det_basis_sets(L, Nu, Nd, alloc, ref, seed, left_upto=c, right_from=c + 2)
+    bond_sets = {}
+    for i in range(c + 1):
+        bond_sets[i] = S[i]
+    for i in range(c + 2, L + 1):
+        bond_sets[i] = T[i]
+    # bond c+1: every charge reachable from both sides, dimension 1 (its tensors are unused)
+    left_q = {(q[0] + LOCAL_CHARGE[n][0], q[1] + LOCAL_CHARGE[n][1]) for q in S[c] for n in range(4)}
+    right_q = {(q[0] - LOCAL_CHARGE[n][0], q[1] - LOCAL_CHARGE[n][1]) for q in T[c + 2] for n in range(4)}
+    mid = sorted(left_q & right_q)
+    bonds = []
+    for i in range(L + 1):
+        if i == c + 1:
+            bonds.append([(q[0], q[1], 1) for q in mid])
+        else:
+            bonds.append([(q[0], q[1], len(bond_sets[i][q])) for q in sorted(bond_sets[i])])
+    data = []
+    for i in range(L):
+        left = [((a, b), d) for a, b, d in bonds[i]]
+        right = [((a, b), d) for a, b, d in bonds[i + 1]]
+        offs, widths, blocks, size = _panel_layout(left, right)
+        A = np.zeros(size, dtype=np.complex128)
+        if i < c:  # left selection: S_{i+1}[b] = S_i[a] + (n,)
+            index = {}
+            for t, (q, d) in enumerate(right):
+                for b, det in enumerate(bond_sets[i + 1][q]):
+                    index[det] = (t, b)
+            for s, (q, d) in enumerate(left):
+                for a, det in enumerate(bond_sets[i][q]):
+                    for n in range(4):
+                        hit = index.get(det + (n,))
+                        if hit is None or (s, n) not in blocks:
+                            continue
+                        t, b = hit
+                        _, col = blocks[(s, n)]
+                        A[offs[s] + a * widths[s] + col + b] = 1.0
+        elif i >= c + 2:  # right selection: T_i[a] = (n,) + T_{i+1}[b]
+            index = {}
+            for t, (q, d) in enumerate(right):
+                for b, det in enumerate(bond_sets[i + 1][q]):
+                    index[det] = (t, b)
+            for s, (q, d) in enumerate(left):
+                for a, det in enumerate(bond_sets[i][q]):
+                    n = det[0]
+                    hit = index.get(det[1:])
+                    if hit is None or (s, n) not in blocks:
+                        continue
+                    t, b = hit
+                    _, col = blocks[(s, n)]
+                    A[offs[s] + a * widths[s] + col + b] = 1.0
+        data.append(A)
+    return bonds, np.concatenate(data), S[c], T[c + 2]
+
+
+def random_state(L, Nu, Nd, D, sigma=1.0, seed=0):
+    """Random block-sparse state with the sector allocation above (complex Gaussian
+    blocks, panel layout).  Returns (bonds, data)."""
+    alloc = sector_allocation(L, Nu, Nd, D, sigma)
+    bonds = [[(q[0], q[1], d) for q, d in sorted(b.items())] for b in alloc]
+    rng = _rng(seed)
+    data = []
+    for i in range(L):
+        left = [((a, b), d) for a, b, d in bonds[i]]
+        right = [((a, b), d) for a, b, d in bonds[i + 1]]
+        size = _panel_layout(left, right)[3]
+        data.append(random_complex(rng, size) / np.sqrt(max(1, D)))
+    return bonds, np.concatenate(data)
