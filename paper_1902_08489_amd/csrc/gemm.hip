@@ -143,7 +143,8 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmTask* __restric
       }
     }
   }
-  // epilogue: lane holds rows 4*lq + e of each 16x16 tile, real column l16
+  // epilogue: register e of a lane holds row lq + 4 e of each 16x16 tile, real column l16
+  // (lane layout of v_mfma_f64_16x16x4f64 on gfx950: A[l%16][l/16], B[l/16][l%16])
   double2* C = (double2*)T.C + bidx * T.bsC;
   const bool accum = T.flags & GEMM_ACCUM;
 #pragma unroll
@@ -155,7 +156,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmTask* __restric
       const int part = rc & 1;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int gr = m0 + wm + i * 16 + 4 * lq + e;
+        const int gr = m0 + wm + i * 16 + lq + 4 * e;
         if (gr < T.m && gc < T.n) {
           double* p = (double*)(C + (int64_t)gr * T.ldc + gc) + part;
           *p = accum ? *p + acc[i][j][e] : acc[i][j][e];

@@ -12,6 +12,7 @@ truncated chains therefore runs with svd_cutoff = 1e-5 (bound ~2e-11); exact cas
 the default 1e-12."""
 import numpy as np
 import pytest
+import torch
 
 import synth
 from oracle import fci, mps as om, propagate, slater
@@ -170,7 +171,6 @@ def test_krylov_exact_and_norm_conserving(ctx, sys6):
 def test_heff_on_determinant_basis_matches_slater_condon(ctx):
     """With determinant bond bases, H_eff at the centre is the FCI matrix on the product
     determinants; sampled outputs equal Slater-Condon sums over all inputs."""
-    import torch
     L, D = 12, 128
     Nu, Nd = 6, 5
     h, eri, _ = synth.integrals(L)
