@@ -99,6 +99,7 @@ def main():
     for _ in range(args.warmup):
         op.apply(tin.data_ptr(), tout.data_ptr())
     flops = op.flops()
+    plan_stats = ctx.counters()
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t0 = time.perf_counter()
@@ -178,6 +179,9 @@ def main():
         "cpu_baseline": cpu,
         "krylov": krylov,
         "check": check,
+        "plan": {"executed_flops_T_stage": plan_stats[1], "executed_flops_final_stage": plan_stats[2],
+                 "T_bytes": plan_stats[3], "tasks": [int(plan_stats[4]), int(plan_stats[5])],
+                 "segments": [int(plan_stats[6]), int(plan_stats[7])]},
     }
     print(json.dumps(line), flush=True)
 

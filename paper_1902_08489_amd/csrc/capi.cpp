@@ -467,6 +467,15 @@ extern "C" tdmps_status tdmps_heff_apply(tdmps_heff h, const void* in, void* out
       h->last_in = in;
       h->last_out = out;
       h->alg_flops = h->plan->alg_flops;
+      Ctx* c = h->ctx;
+      c->counters[0] = h->alg_flops;
+      c->counters[1] = h->plan->p1.flops;
+      c->counters[2] = h->plan->p2.flops;
+      c->counters[3] = (double)h->plan->T.bytes;
+      c->counters[4] = (double)h->plan->p1.tasks.size();
+      c->counters[5] = (double)h->plan->p2.tasks.size();
+      c->counters[6] = (double)h->plan->p1.segs.size();
+      c->counters[7] = (double)h->plan->p2.segs.size();
     }
     h->plan->launch(h->ctx, h->precision);
     dev_sync(h->ctx->stream);

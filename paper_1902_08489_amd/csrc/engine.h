@@ -184,9 +184,12 @@ struct GemmPlan {
   void add_seg(const cplx* A, int64_t bsA, int64_t rsA, int lda, int opA, const cplx* B, int64_t bsB, int64_t rsB,
                int ldb, int opB, int k, int nred, cplx alpha);
   // device copies of the task lists (finalize) and asynchronous launch
-  DevBuf dsegs, dtasks[2];
-  int ntask[2] = {0, 0};
-  int64_t ntiles[2] = {0, 0};
+  static constexpr int NCFG = 3;
+  DevBuf dsegs, dtasks[NCFG], dtile[NCFG], wspace, dred;
+  std::vector<int64_t> red_base;
+  int nred_tasks = 0;
+  int ntask[NCFG] = {0, 0, 0};
+  int64_t ntiles[NCFG] = {0, 0, 0};
   bool final_ = false;
   void finalize(Ctx* ctx);
   void launch(Ctx* ctx, int precision);

@@ -37,6 +37,13 @@ struct GemmSeg {
   cplx alpha;
 };
 
+// Split-K partial sums: C (+)= sum_{q < nparts} parts[q] (each part m x n, contiguous).
+struct ReduceTask {
+  cplx* C;
+  const cplx* parts;
+  int32_t m, n, ldc, nparts, accum;
+};
+
 // ---------------------------------------------------------------- strided block copies
 // dst[r*dst_ld + c] (+)= op(src[(ridx?ridx[r]:r)*src_rs + (cidx?cidx[c]:c)*src_cs]) * rs[r] * cs[c]
 struct CopyTask {
@@ -77,8 +84,9 @@ void dev_event_record(void* e, void* stream);
 float dev_event_elapsed_ms(void* a, void* b);  // synchronises on b
 
 // launchers (all asynchronous on `stream`)
-void launch_gemm(const GemmTask* tasks, const GemmSeg* segs, int ntasks, int64_t total_tiles, int cfg, int precision,
-                 void* stream);
+void launch_gemm(const GemmTask* tasks, const GemmSeg* segs, const int32_t* tile_task, int64_t total_tiles, int cfg,
+                 int precision, void* stream);
+void launch_reduce(const ReduceTask* tasks, int ntasks, void* stream);
 int gemm_tile_m(int cfg);
 int gemm_tile_n(int cfg);
 void launch_copy(const CopyTask* tasks, int ntasks, void* stream);

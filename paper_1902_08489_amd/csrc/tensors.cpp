@@ -146,18 +146,96 @@ void GemmPlan::finalize(Ctx* ctx) {
   for (auto& t : tasks)
     if (t.m > 0 && t.n > 0 && t.nbatch > 0 && (t.nseg > 0 || !(t.flags & GEMM_ACCUM))) keep.push_back(t);
   if (keep.empty()) return;
-  if (!segs.empty()) {
-    dsegs = DevBuf(segs.size() * sizeof(GemmSeg));
-    dev_h2d(dsegs.p, segs.data(), segs.size() * sizeof(GemmSeg), ctx->stream);
+  // Split-K: a task whose reduction is long (many channels) is cut into parts of about
+  // KSPLIT complex k; parts write private partial outputs that a reduction kernel adds in
+  // a fixed order (deterministic, no atomics).
+  const int64_t KSPLIT = 1024;
+  std::vector<GemmTask> out;
+  std::vector<GemmSeg> nsegs;
+  std::vector<ReduceTask> red;
+  std::vector<std::pair<size_t, int64_t>> part_of;  // (task index in out, offset in workspace)
+  int64_t ws = 0;
+  for (auto& t : keep) {
+    int64_t work = 0;
+    for (int s = t.seg0; s < t.seg0 + t.nseg; ++s) work += (int64_t)segs[s].nred * segs[s].k;
+    int nparts = (t.nbatch == 1 && work > 2 * KSPLIT) ? (int)std::min<int64_t>(64, (work + KSPLIT - 1) / KSPLIT) : 1;
+    if (nparts <= 1) {
+      GemmTask c = t;
+      c.seg0 = (int32_t)nsegs.size();
+      for (int s = t.seg0; s < t.seg0 + t.nseg; ++s) nsegs.push_back(segs[s]);
+      out.push_back(c);
+      continue;
+    }
+    const int64_t target = (work + nparts - 1) / nparts;
+    ReduceTask rt;
+    rt.C = t.C;
+    rt.parts = nullptr;
+    rt.m = t.m;
+    rt.n = t.n;
+    rt.ldc = t.ldc;
+    rt.accum = (t.flags & GEMM_ACCUM) ? 1 : 0;
+    int64_t base = ws;
+    int made = 0;
+    GemmTask cur = t;
+    cur.flags = 0;
+    cur.ldc = t.n;
+    cur.bsC = 0;
+    cur.nseg = 0;
+    cur.seg0 = (int32_t)nsegs.size();
+    int64_t acc = 0;
+    auto close = [&]() {
+      if (cur.nseg == 0) return;
+      part_of.push_back({out.size(), base + (int64_t)made * t.m * t.n});
+      out.push_back(cur);
+      ++made;
+      cur.nseg = 0;
+      cur.seg0 = (int32_t)nsegs.size();
+      acc = 0;
+    };
+    for (int s = t.seg0; s < t.seg0 + t.nseg; ++s) {
+      const GemmSeg& g = segs[s];
+      int r = 0;
+      while (r < g.nred) {
+        int64_t room = target - acc;
+        int take = (int)std::max<int64_t>(1, std::min<int64_t>(g.nred - r, room / std::max(1, g.k)));
+        GemmSeg v = g;
+        v.A = g.A + (int64_t)r * g.rsA;
+        v.B = g.B + (int64_t)r * g.rsB;
+        v.nred = take;
+        nsegs.push_back(v);
+        cur.nseg++;
+        acc += (int64_t)take * g.k;
+        r += take;
+        if (acc >= target) close();
+      }
+    }
+    close();
+    rt.nparts = made;
+    ws += (int64_t)made * t.m * t.n;
+    red.push_back(rt);
+    red_base.push_back(base);
   }
-  // tile configuration per task: small outputs take the small tile
-  for (int cfg = 0; cfg < 2; ++cfg) {
+  if (ws > 0) {
+    wspace = DevBuf(ws * sizeof(cplx));
+    for (auto& po : part_of) out[po.first].C = wspace.c() + po.second;
+    for (size_t k = 0; k < red.size(); ++k) red[k].parts = wspace.c() + red_base[k];
+    dred = DevBuf(red.size() * sizeof(ReduceTask));
+    dev_h2d(dred.p, red.data(), red.size() * sizeof(ReduceTask), ctx->stream);
+    nred_tasks = (int)red.size();
+  }
+  if (!nsegs.empty()) {
+    dsegs = DevBuf(nsegs.size() * sizeof(GemmSeg));
+    dev_h2d(dsegs.p, nsegs.data(), nsegs.size() * sizeof(GemmSeg), ctx->stream);
+  }
+  // tile shape per task: 64x64 for wide outputs, 128x32 for tall narrow ones (the
+  // channel-stacked L*theta products), 32x32 otherwise
+  auto pick = [](const GemmTask& t) { return t.n > 40 && t.m > 40 ? 0 : (t.m >= 96 ? 2 : 1); };
+  for (int cfg = 0; cfg < NCFG; ++cfg) {
     std::vector<GemmTask> sel;
     int64_t base = 0;
     int tm = gemm_tile_m(cfg), tn = gemm_tile_n(cfg);
-    for (auto t : keep) {
-      bool big = (t.m > 40 && t.n > 40);
-      if ((cfg == 0) != big) continue;
+    for (auto t : out) {
+      if (pick(t) != cfg) continue;
       t.tiles_m = (t.m + tm - 1) / tm;
       t.tiles_n = (t.n + tn - 1) / tn;
       t.tile_base = base;
@@ -169,14 +247,22 @@ void GemmPlan::finalize(Ctx* ctx) {
     if (sel.empty()) continue;
     dtasks[cfg] = DevBuf(sel.size() * sizeof(GemmTask));
     dev_h2d(dtasks[cfg].p, sel.data(), sel.size() * sizeof(GemmTask), ctx->stream);
+    std::vector<int32_t> tt((size_t)base);
+    for (size_t k = 0; k < sel.size(); ++k) {
+      int64_t nt = (int64_t)sel[k].nbatch * sel[k].tiles_m * sel[k].tiles_n;
+      std::fill(tt.begin() + sel[k].tile_base, tt.begin() + sel[k].tile_base + nt, (int32_t)k);
+    }
+    dtile[cfg] = DevBuf(tt.size() * sizeof(int32_t));
+    dev_h2d(dtile[cfg].p, tt.data(), tt.size() * sizeof(int32_t), ctx->stream);
   }
 }
 
 void GemmPlan::launch(Ctx* ctx, int precision) {
-  for (int cfg = 0; cfg < 2; ++cfg)
+  for (int cfg = 0; cfg < NCFG; ++cfg)
     if (ntask[cfg] > 0)
-      launch_gemm((const GemmTask*)dtasks[cfg].p, (const GemmSeg*)dsegs.p, ntask[cfg], ntiles[cfg], cfg, precision,
-                  ctx->stream);
+      launch_gemm((const GemmTask*)dtasks[cfg].p, (const GemmSeg*)dsegs.p, (const int32_t*)dtile[cfg].p, ntiles[cfg],
+                  cfg, precision, ctx->stream);
+  if (nred_tasks > 0) launch_reduce((const ReduceTask*)dred.p, nred_tasks, ctx->stream);
 }
 
 void GemmPlan::run(Ctx* ctx, int precision) {
