@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <type_traits>
 
 #include "common.h"
 #include "kernels.h"
@@ -140,24 +141,58 @@ __device__ __forceinline__ bool next_step(const GemmSeg* __restrict__ segs, cons
   return ++it.s < T.seg0 + T.nseg;
 }
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// Precision of the products (operands are FP64 complex in HBM in every mode):
+//   P64  : FP64 MFMA 16x16x4               (LDS: double2)
+//   P32  : FP32 MFMA 16x16x4, FP32 accumulate (LDS: float2)
+//   PBF3 : bf16 split x = hi + lo of the FP32-rounded operand, products hi*hi + hi*lo + lo*hi
+//          on the 16x16x32 bf16 MFMA with FP32 accumulate (LDS: realified hi / lo planes)
+enum { P64 = 0, P32 = 1, PBF3 = 2 };
+
+template <int BM, int BN, int PREC>
+struct Smem;
 template <int BM, int BN>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmTask* __restrict__ tasks,
-                                                       const GemmSeg* __restrict__ segs,
-                                                       const int32_t* __restrict__ tile_task, int64_t total_tiles) {
+struct Smem<BM, BN, P64> {
+  double2 A[BM][17];
+  double2 B[16][BN + 1];
+};
+template <int BM, int BN>
+struct Smem<BM, BN, P32> {
+  float2 A[BM][17];
+  float2 B[16][BN + 1];
+};
+template <int BM, int BN>
+struct Smem<BM, BN, PBF3> {
+  // A' rows (realified k, 32 per stage) and B'^T rows (realified column, 32 k), hi and lo
+  __bf16 Ah[BM][40], Al[BM][40];
+  __bf16 Bh[2 * BN][40], Bl[2 * BN][40];
+};
+
+__device__ __forceinline__ void split_bf16(double x, __bf16& h, __bf16& l) {
+  const float f = (float)x;
+  h = (__bf16)f;
+  l = (__bf16)(f - (float)h);
+}
+
+template <int BM, int BN, int PREC>
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmTask* __restrict__ tasks,
+                                                   const GemmSeg* __restrict__ segs,
+                                                   const int32_t* __restrict__ tile_task, int64_t total_tiles) {
   constexpr int BK = 16;             // complex k per LDS stage
   constexpr int WM = BM / 2;         // complex rows per wave
   constexpr int WN = BN / 2;         // complex columns per wave
   constexpr int TM = WM / 16;        // 16x16 MFMA tiles along m
   constexpr int TN = (2 * WN) / 16;  // along real n
-  __shared__ double2 As[BM][BK + 1];
-  __shared__ double2 Bs[BK][BN + 1];
+  typedef typename std::conditional<PREC == P64, d4, f4>::type acc_t;
+  __shared__ Smem<BM, BN, PREC> sm;
 
   // One tile per workgroup.  Workgroup w runs on XCD w % 8; tiles are numbered so that
   // each XCD takes a contiguous range, keeping neighbouring tiles of a task in one L2.
   const int64_t per_xcd = (total_tiles + 7) / 8;
   const int64_t tile = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (tile >= total_tiles) return;
-  {
   const int ti = tile_task[tile];
   const GemmTask T = tasks[ti];
   const int64_t local = tile - T.tile_base;
@@ -172,22 +207,79 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmTask* __restric
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
   const int l16 = lane & 15, lq = lane >> 4;
 
-  d4 acc[TM][TN];
+  acc_t acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
   Stage<BM, BN, BK> st;
   StepIt it{T.seg0, 0, 0};
   bool have = T.nseg > 0;
-  // skip empty segments
   while (have && (segs[it.s].k <= 0 || segs[it.s].nred <= 0)) {
     if (++it.s >= T.seg0 + T.nseg) have = false;
   }
   if (have) st.load(segs[it.s], T, bidx, it.r, it.k0, m0, n0, tid);
   while (have) {
-    st.store(As, Bs, segs[it.s], tid);
+    // registers -> LDS in the precision's layout
+    {
+      const GemmSeg& S = segs[it.s];
+      const bool transA = S.opA == OP_T || S.opA == OP_C;
+      const bool transB = S.opB == OP_T || S.opB == OP_C;
+#pragma unroll
+      for (int q = 0; q < Stage<BM, BN, BK>::NA; ++q) {
+        const int e = tid + q * 256;
+        int rr, kk;
+        if (!transA) {
+          rr = e / BK;
+          kk = e - rr * BK;
+        } else {
+          kk = e / BM;
+          rr = e - kk * BM;
+        }
+        const double2 v = st.ra[q];
+        if constexpr (PREC == P64) {
+          sm.A[rr][kk] = v;
+        } else if constexpr (PREC == P32) {
+          sm.A[rr][kk] = make_float2((float)v.x, (float)v.y);
+        } else {
+          split_bf16(v.x, sm.Ah[rr][2 * kk], sm.Al[rr][2 * kk]);
+          split_bf16(v.y, sm.Ah[rr][2 * kk + 1], sm.Al[rr][2 * kk + 1]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < Stage<BM, BN, BK>::NB; ++q) {
+        const int e = tid + q * 256;
+        int kk, cc;
+        if (!transB) {
+          kk = e / BN;
+          cc = e - kk * BN;
+        } else {
+          cc = e / BK;
+          kk = e - cc * BK;
+        }
+        const double2 v = st.rb[q];
+        if constexpr (PREC == P64) {
+          sm.B[kk][cc] = v;
+        } else if constexpr (PREC == P32) {
+          sm.B[kk][cc] = make_float2((float)v.x, (float)v.y);
+        } else {
+          // B' = [[Re, Im], [-Im, Re]] per complex element, stored transposed (column-major)
+          __bf16 rh, rl, ih, il, nh, nl;
+          split_bf16(v.x, rh, rl);
+          split_bf16(v.y, ih, il);
+          split_bf16(-v.y, nh, nl);
+          sm.Bh[2 * cc][2 * kk] = rh;
+          sm.Bl[2 * cc][2 * kk] = rl;
+          sm.Bh[2 * cc + 1][2 * kk] = ih;
+          sm.Bl[2 * cc + 1][2 * kk] = il;
+          sm.Bh[2 * cc][2 * kk + 1] = nh;
+          sm.Bl[2 * cc][2 * kk + 1] = nl;
+          sm.Bh[2 * cc + 1][2 * kk + 1] = rh;
+          sm.Bl[2 * cc + 1][2 * kk + 1] = rl;
+        }
+      }
+    }
     __syncthreads();
     StepIt nx = it;
     bool more = next_step(segs, T, nx, BK);
@@ -197,34 +289,62 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmTask* __restric
       more = ++nx.s < T.seg0 + T.nseg;
     }
     if (more) st.load(segs[nx.s], T, bidx, nx.r, nx.k0, m0, n0, tid);
-#pragma unroll
-    for (int kr = 0; kr < 2 * BK; kr += 4) {
-      const int kreal = kr + lq;
-      const int kc = kreal >> 1, kp = kreal & 1;
-      double a[TM], bb[TN];
+    if constexpr (PREC == PBF3) {
+      bf8 ah[TM], al[TM];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        double2 av = As[wm + i * 16 + l16][kc];
-        a[i] = kp ? av.y : av.x;
+        ah[i] = *(const bf8*)&sm.Ah[wm + i * 16 + l16][8 * lq];
+        al[i] = *(const bf8*)&sm.Al[wm + i * 16 + l16][8 * lq];
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int rc = 2 * wn + j * 16 + l16;
-        double2 bv = Bs[kc][rc >> 1];
-        const int cp = rc & 1;
-        bb[j] = kp == 0 ? (cp == 0 ? bv.x : bv.y) : (cp == 0 ? -bv.y : bv.x);
+        const bf8 bh = *(const bf8*)&sm.Bh[rc][8 * lq];
+        const bf8 bl = *(const bf8*)&sm.Bl[rc][8 * lq];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+        }
       }
+    } else {
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+      for (int kr = 0; kr < 2 * BK; kr += 4) {
+        const int kreal = kr + lq;
+        const int kc = kreal >> 1, kp = kreal & 1;
+        typedef typename std::conditional<PREC == P64, double, float>::type r_t;
+        r_t a[TM], bb[TN];
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
+        for (int i = 0; i < TM; ++i) {
+          const auto av = sm.A[wm + i * 16 + l16][kc];
+          a[i] = kp ? av.y : av.x;
+        }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int rc = 2 * wn + j * 16 + l16;
+          const auto bv = sm.B[kc][rc >> 1];
+          const int cp = rc & 1;
+          bb[j] = kp == 0 ? (cp == 0 ? bv.x : bv.y) : (cp == 0 ? -bv.y : bv.x);
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            if constexpr (PREC == P64)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
+            else
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], bb[j], acc[i][j], 0, 0, 0);
+          }
+      }
     }
     __syncthreads();
     it = nx;
     have = more;
   }
-  // epilogue: register e of a lane holds row lq + 4 e of each 16x16 tile, real column l16
-  // (lane layout of v_mfma_f64_16x16x4f64 on gfx950: A[l%16][l/16], B[l/16][l%16])
+  // Epilogue.  Output lane layouts on gfx950 (read off the hardware): register e of lane l
+  // holds row l/16 + 4e of a 16x16 tile for the f64 MFMA and row 4(l/16) + e for the f32
+  // and bf16 MFMAs; column l%16 in all cases.
   double2* C = (double2*)T.C + bidx * T.bsC;
   const bool accum = T.flags & GEMM_ACCUM;
 #pragma unroll
@@ -236,15 +356,15 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmTask* __restric
       const int part = rc & 1;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int gr = m0 + wm + i * 16 + lq + 4 * e;
+        const int row = PREC == P64 ? lq + 4 * e : 4 * lq + e;
+        const int gr = m0 + wm + i * 16 + row;
         if (gr < T.m && gc < T.n) {
           double* p = (double*)(C + (int64_t)gr * T.ldc + gc) + part;
-          *p = accum ? *p + acc[i][j][e] : acc[i][j][e];
+          const double v = (double)acc[i][j][e];
+          *p = accum ? *p + v : v;
         }
       }
     }
-  __syncthreads();
-  }
 }
 
 // Deterministic split-K reduction: C (+)= sum_s parts[s] in fixed order.
@@ -288,19 +408,29 @@ void launch_reduce(const ReduceTask* tasks, int ntasks, void* stream) {
 int gemm_tile_m(int cfg) { return cfg == 0 ? 64 : (cfg == 1 ? 32 : 128); }
 int gemm_tile_n(int cfg) { return cfg == 0 ? 64 : 32; }
 
-void launch_gemm(const GemmTask* tasks, const GemmSeg* segs, const int32_t* tile_task, int64_t total_tiles, int cfg,
-                 int precision, void* stream) {
-  if (total_tiles <= 0) return;
-  (void)precision;
+template <int BM, int BN>
+void launch_cfg(const GemmTask* tasks, const GemmSeg* segs, const int32_t* tile_task, int64_t total_tiles, int precision,
+                hipStream_t stream) {
   const int64_t grid = 8 * ((total_tiles + 7) / 8);
   TDMPS_REQUIRE(grid < ((int64_t)1 << 31), TDMPS_ERR_ARG, "too many GEMM tiles in one launch");
   dim3 g((unsigned)grid), block(256);
-  if (cfg == 0)
-    hipLaunchKernelGGL((gemm_f64_kernel<64, 64>), g, block, 0, (hipStream_t)stream, tasks, segs, tile_task, total_tiles);
-  else if (cfg == 1)
-    hipLaunchKernelGGL((gemm_f64_kernel<32, 32>), g, block, 0, (hipStream_t)stream, tasks, segs, tile_task, total_tiles);
+  if (precision == TDMPS_FP32)
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, P32>), g, block, 0, stream, tasks, segs, tile_task, total_tiles);
+  else if (precision == TDMPS_BF16X3)
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, PBF3>), g, block, 0, stream, tasks, segs, tile_task, total_tiles);
   else
-    hipLaunchKernelGGL((gemm_f64_kernel<128, 32>), g, block, 0, (hipStream_t)stream, tasks, segs, tile_task, total_tiles);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, P64>), g, block, 0, stream, tasks, segs, tile_task, total_tiles);
+}
+
+void launch_gemm(const GemmTask* tasks, const GemmSeg* segs, const int32_t* tile_task, int64_t total_tiles, int cfg,
+                 int precision, void* stream) {
+  if (total_tiles <= 0) return;
+  if (cfg == 0)
+    launch_cfg<64, 64>(tasks, segs, tile_task, total_tiles, precision, (hipStream_t)stream);
+  else if (cfg == 1)
+    launch_cfg<32, 32>(tasks, segs, tile_task, total_tiles, precision, (hipStream_t)stream);
+  else
+    launch_cfg<128, 32>(tasks, segs, tile_task, total_tiles, precision, (hipStream_t)stream);
   check(hipGetLastError(), "gemm launch");
 }
 

@@ -1,0 +1,72 @@
+"""Mixed precision: block products in FP32 or BF16-split (hi*hi + hi*lo + lo*hi with FP32
+accumulation) while SVD truncation and the Krylov algebra stay FP64.  Errors of the state,
+energy, norm and dipole are measured against the FP64 GPU run and the oracle; the bounds
+are set from the unit roundoff of each mode (FP32: 2^-24, BF16 split: about 2^-16 per
+product) with a margin for accumulation."""
+import numpy as np
+import pytest
+import torch  # noqa: F401  (device initialisation shared with the other GPU tests)
+
+import synth
+from oracle import fci, mps as om, propagate
+from paper_1902_08489_amd import tdmps as T
+
+from _mpshelp import blocks_to_oracle, dense
+
+pytestmark = pytest.mark.gpu
+BOUND = {T.FP32: 1e-5, T.BF16X3: 1e-3}
+
+
+@pytest.fixture(scope="module")
+def setup():
+    T.load()
+    ctx = T.Context(0)
+    L = 8
+    h, eri, _ = synth.integrals(L)
+    mu = synth.dipole_matrix(L)
+    occ = synth.ionized_determinant(L, 8)
+    Q = synth.occ_charge(occ)
+    space = fci.Space.sector(L, *Q)
+    H = fci.hamiltonian(space, h, eri)
+    return dict(ctx=ctx, L=L, h=h, eri=eri, mu=mu, occ=occ, Q=Q, space=space, H=H,
+                mpo=T.MPO.from_integrals(ctx, h, eri), dip=T.MPO.one_body(ctx, mu))
+
+
+@pytest.mark.parametrize("prec", [T.FP32, T.BF16X3])
+def test_apply_H_precision_error(setup, prec):
+    s = setup
+    bonds, data = synth.random_state(s["L"], *s["Q"], 48, seed=21)
+    psi = T.MPS.from_blocks(s["ctx"], bonds, data)
+    ref, _ = T.apply_H(s["mpo"], 1.0, psi, [], T.fit_params(Dmax=200, n_sweeps=3))
+    low, _ = T.apply_H(s["mpo"], 1.0, psi, [], T.fit_params(Dmax=200, n_sweeps=3, precision=prec))
+    exact = s["space"].embed(s["H"] @ s["space"].restrict(om.to_full(blocks_to_oracle(bonds, data))))
+    e64 = np.linalg.norm(dense(ref) - exact) / np.linalg.norm(exact)
+    elow = np.linalg.norm(dense(low) - exact) / np.linalg.norm(exact)
+    print(f"precision {prec}: rel err vs oracle {elow:.2e} (fp64 {e64:.2e})")
+    assert e64 < 1e-10
+    assert elow < BOUND[prec]
+
+
+@pytest.mark.parametrize("prec", [T.FP32, T.BF16X3])
+def test_krylov_observables_precision_error(setup, prec):
+    """Three Krylov steps (m = 5, D = 64): energy, norm and dipole against the FP64 GPU run
+    and the exact propagation."""
+    s = setup
+    res = {}
+    for p in (T.FP64, prec):
+        psi = T.MPS.from_determinant(s["ctx"], s["occ"])
+        prm = T.fit_params(Dmax=64, n_sweeps=2, precision=p)
+        for _ in range(3):
+            psi, _, _ = T.krylov_step(s["mpo"], psi, 0.05, 5, True, prm)
+        n2 = T.overlap(psi, psi).real
+        res[p] = (n2, T.expect(s["mpo"], psi, psi).real / n2, T.expect(s["dip"], psi, psi).real / n2)
+    v0 = s["space"].restrict(om.to_full(om.from_occ(s["occ"])))
+    ve = propagate.exact(s["H"], v0, 0.15)
+    Mu = fci.one_body_operator(s["space"], s["mu"])
+    exact = (1.0, fci.expectation(s["H"], ve).real, fci.expectation(Mu, ve).real)
+    names = ("norm", "energy", "dipole")
+    for k in range(3):
+        rel = abs(res[prec][k] - res[T.FP64][k]) / abs(res[T.FP64][k])
+        print(f"precision {prec} {names[k]}: {res[prec][k]:.12f} fp64 {res[T.FP64][k]:.12f} exact {exact[k]:.12f} "
+              f"rel {rel:.2e}")
+        assert rel < BOUND[prec]
