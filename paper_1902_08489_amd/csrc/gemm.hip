@@ -155,8 +155,8 @@ template <int BM, int BN, int PREC>
 struct Smem;
 template <int BM, int BN>
 struct Smem<BM, BN, P64> {
-  double2 A[BM][17];
-  double2 B[16][BN + 1];
+  double2 A[BM][9];
+  double2 B[8][BN + 1];
 };
 template <int BM, int BN>
 struct Smem<BM, BN, P32> {
@@ -177,14 +177,14 @@ __device__ __forceinline__ void split_bf16(double x, __bf16& h, __bf16& l) {
 }
 
 template <int BM, int BN, int PREC>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmTask* __restrict__ tasks,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void gemm_kernel(const GemmTask* __restrict__ tasks,
                                                    const GemmSeg* __restrict__ segs,
                                                    const int32_t* __restrict__ tile_task, int64_t total_tiles) {
-  constexpr int BK = 16;             // complex k per LDS stage
-  constexpr int WM = BM / 2;         // complex rows per wave
-  constexpr int WN = BN / 2;         // complex columns per wave
-  constexpr int TM = WM / 16;        // 16x16 MFMA tiles along m
-  constexpr int TN = (2 * WN) / 16;  // along real n
+  constexpr int BK = PREC == P64 ? 8 : 16;  // complex k per LDS stage (FP64: fewer live registers)
+  constexpr int WM = BM / 2;                 // complex rows per wave
+  constexpr int WN = BN / 2;                 // complex columns per wave
+  constexpr int TM = WM / 16;                // 16x16 MFMA tiles along m
+  constexpr int TN = (2 * WN) / 16;          // along real n
   typedef typename std::conditional<PREC == P64, d4, f4>::type acc_t;
   __shared__ Smem<BM, BN, PREC> sm;
 
