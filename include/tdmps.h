@@ -93,9 +93,11 @@ const char* tdmps_last_error(void);
  * stream) or a borrowed hipStream_t that must outlive the context. */
 tdmps_status tdmps_ctx_create(int32_t device, void* hip_stream, tdmps_ctx* out);
 tdmps_status tdmps_ctx_destroy(tdmps_ctx ctx);
-/* Counters of the last operation: out[0] = algorithmic flops of the H_eff contractions,
- * out[1] = their kernel time in ms, out[2] = env-update flops, out[3] = env time ms,
- * out[4] = SVD time ms, out[5] = number of two-site updates. */
+/* Counters of the last operation (fit, time step or expectation value):
+ * out[0] = algorithmic flops of the H_eff contractions, out[1] = executed H_eff flops,
+ * out[2..6] = wall seconds spent in H_eff, environment updates, SVD truncation, premix
+ * and sandwiches (sandwich time includes its own environment updates), out[7] = executed
+ * environment-update flops.  After tdmps_heff_apply planning, out[0..7] describe the plan. */
 tdmps_status tdmps_ctx_counters(tdmps_ctx ctx, double* out8);
 tdmps_status tdmps_ctx_reset_counters(tdmps_ctx ctx);
 

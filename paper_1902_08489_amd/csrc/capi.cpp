@@ -38,8 +38,12 @@ Contractor make_contractor(Ctx* ctx, const tdmps_fit_params* prm) {
 void publish(Ctx* ctx, const Contractor& C) {
   ctx->counters[0] = C.heff_alg_flops;
   ctx->counters[1] = C.heff_flops;
-  ctx->counters[2] = C.env_flops;
-  ctx->counters[3] = C.mix_flops;
+  ctx->counters[2] = C.t_heff;
+  ctx->counters[3] = C.t_env;
+  ctx->counters[4] = C.t_svd;
+  ctx->counters[5] = C.t_mix;
+  ctx->counters[6] = C.t_sandwich;
+  ctx->counters[7] = C.env_flops;
 }
 
 void check_prm(const tdmps_fit_params* p) {

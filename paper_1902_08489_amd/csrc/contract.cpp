@@ -40,6 +40,12 @@ struct MixRow {
 };
 
 SideOps build_ops(Contractor& C, const Env& E, const MpoHost& W, int site, bool left) {
+  const double t0 = wall_seconds();
+  struct Acc {
+    Contractor& C;
+    double t0;
+    ~Acc() { C.t_mix += wall_seconds() - t0; }
+  } acc_{C, t0};
   SideOps ops;
   const int mid_cut = left ? site + 1 : site;
   const MpoCut& mc = W.cut[mid_cut];
@@ -211,6 +217,7 @@ static std::vector<std::pair<Charge, int>> cut_groups(const MpoCut& c) {
 Env env_left_update(Contractor& C, const SideOps& ops, const Mps*, const cplx* bra_site, const SiteLayout& bl,
                     const Bond& bra_l, const Bond& bra_r, const cplx* ket_site, const SiteLayout& kl,
                     const Bond& ket_l, const Bond& ket_r, const MpoHost& W) {
+  const double t0 = wall_seconds();
   const MpoCut& mc = W.cut[ops.cut];
   Env out;
   out.cut = ops.cut;
@@ -303,12 +310,14 @@ Env env_left_update(Contractor& C, const SideOps& ops, const Mps*, const cplx* b
   }
   p2.run(C.ctx, C.precision);
   C.env_flops += p1.flops + p2.flops;
+  C.t_env += wall_seconds() - t0;
   return out;
 }
 
 Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, const SiteLayout& bl, const Bond& bra_l,
                      const Bond& bra_r, const cplx* ket_site, const SiteLayout& kl, const Bond& ket_l,
                      const Bond& ket_r, const MpoHost& W) {
+  const double t0 = wall_seconds();
   const MpoCut& mc = W.cut[ops.cut];
   Env out;
   out.cut = ops.cut;
@@ -398,6 +407,7 @@ Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, co
   }
   p2.run(C.ctx, C.precision);
   C.env_flops += p1.flops + p2.flops;
+  C.t_env += wall_seconds() - t0;
   return out;
 }
 
@@ -410,11 +420,13 @@ void HeffPlan::launch(Ctx* ctx, int precision) {
 void heff_apply(Contractor& C, const SideOps& lops, const SideOps& rops, const cplx* theta_in, const TwoLayout& kl,
                 const Bond& ket_l, const Bond& ket_r, cplx* theta_out, const TwoLayout& bl, const Bond& bra_l,
                 const Bond& bra_r, cplx alpha, bool accumulate, double* alg_flops) {
+  const double t0 = wall_seconds();
   auto plan = heff_plan(C, lops, rops, theta_in, kl, ket_l, ket_r, theta_out, bl, bra_l, bra_r, alpha, accumulate);
   plan->launch(C.ctx, C.precision);
   dev_sync(C.ctx->stream);
   C.heff_flops += plan->p1.flops + plan->p2.flops;
   if (alg_flops) *alg_flops = plan->alg_flops;
+  C.t_heff += wall_seconds() - t0;
 }
 
 std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const SideOps& rops, const cplx* theta_in,
@@ -603,6 +615,12 @@ void form_theta(Contractor& C, const Mps* m, int i, cplx* theta, const TwoLayout
 }
 
 cplx sandwich(Contractor& C, const MpoHost& O, const Mps* bra, const Mps* ket) {
+  const double t0 = wall_seconds();
+  struct Acc {
+    Contractor& C;
+    double t0;
+    ~Acc() { C.t_sandwich += wall_seconds() - t0; }
+  } acc_{C, t0};
   TDMPS_REQUIRE(bra->L == ket->L && bra->L == O.L, TDMPS_ERR_ARG, "length mismatch");
   TDMPS_REQUIRE(bra->total == ket->total, TDMPS_ERR_SECTOR, "bra and ket have different total charge");
   Env E = env_left_boundary(C.ctx, bra->bond[0], ket->bond[0]);

@@ -224,7 +224,11 @@ struct Contractor {
   int batched = 1;
   double heff_flops = 0, env_flops = 0, mix_flops = 0;
   double heff_alg_flops = 0;
+  // wall-clock seconds per phase (every phase ends with a stream synchronisation)
+  double t_heff = 0, t_env = 0, t_mix = 0, t_svd = 0, t_sandwich = 0;
 };
+
+double wall_seconds();
 
 Mps* mps_new(Ctx* ctx, int L, const std::vector<Bond>& bonds);
 Mps* mps_clone(const Mps* m);

@@ -60,11 +60,27 @@ struct CopyTask {
 // ---------------------------------------------------------------- one-sided Jacobi SVD
 // Matrix j holds k vectors of length ell (column-major G, column stride ell) and the k x k
 // accumulated rotation V (column-major, column stride k).
+// Columns are grouped in blocks of SVD_BLOCK; nblk = number of blocks rounded up to an even
+// count (at least 2), pair_base = exclusive prefix of nblk/2 over the matrices of a batch.
+constexpr int SVD_BLOCK = 8;
 struct SvdMat {
   cplx* G;
   cplx* V;
-  int32_t ell, k, kpad, pair_base;  // pair_base: exclusive prefix of kpad/2 over matrices
-  double thr;                       // pairs with |g_p^H g_q| <= thr max(|g_p|, |g_q|) are orthogonal
+  int32_t ell, k, nblk, pair_base;
+  double thr;  // pairs with |g_p^H g_q| <= thr max(|g_p|, |g_q|) are orthogonal
+};
+
+// Batched Householder QR (panels of QR_PANEL columns) of G (ell x k, column-major), n = nsv =
+// min(ell, k).  T: per matrix ceil(n / QR_PANEL) row-major QR_PANEL x QR_PANEL compact-WY
+// factors; X: k x n; V: n x n; B: ell x n; cb_base: exclusive prefix of ceil(k / QR_PANEL).
+constexpr int QR_PANEL = 16;
+struct QrMat {
+  cplx* G;
+  cplx* T;
+  cplx* X;
+  cplx* V;
+  cplx* B;
+  int32_t ell, k, nsv, cb_base;
 };
 
 // runtime
@@ -91,9 +107,19 @@ int gemm_tile_m(int cfg);
 int gemm_tile_n(int cfg);
 void launch_copy(const CopyTask* tasks, int ntasks, void* stream);
 void launch_svd_init(const SvdMat* mats, int nmats, void* stream);  // V = identity
+// One round (block pairs of the circle schedule) for all matrices; total_pairs = sum nblk/2;
+// rot_counter is incremented once per block pair that rotated.
 void launch_svd_round(const SvdMat* mats, int nmats, int64_t total_pairs, int round, double tol, int32_t* rot_counter,
                       void* stream);
 void launch_svd_norms(const SvdMat* mats, int nmats, int max_k, double* sigma_out, void* stream);
 void launch_scale(cplx* x, int64_t n, cplx alpha, void* stream);
+// QR preconditioning of the Jacobi SVD: factor panel j0 (one workgroup per matrix); apply
+// panel j0 to the trailing columns of G (mode 0) or Q's panel to B (mode 1) over total_blocks
+// = sum ceil(k / QR_PANEL) column blocks; X = R^H; finish: B = [V; 0], X <- X Sigma^{-1} with
+// sigma[j * max_n + c] the column norms of X.
+void launch_qr_panel(const QrMat* mats, int nmats, int j0, void* stream);
+void launch_qr_apply(const QrMat* mats, int nmats, int total_blocks, int j0, int mode, void* stream);
+void launch_qr_rt(const QrMat* mats, int nmats, void* stream);
+void launch_qr_finish(const QrMat* mats, int nmats, const double* sigma, int max_k, void* stream);
 
 }  // namespace tdmps

@@ -1,4 +1,4 @@
-// Strided block copies and the batched one-sided Jacobi SVD (FP64).
+// Strided block copies and the batched block one-sided Jacobi SVD (FP64).
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -68,67 +68,246 @@ __device__ __forceinline__ int find_mat(const SvdMat* __restrict__ mats, int n, 
   return lo;
 }
 
-__device__ __forceinline__ void rotate(double2* x, double2* y, int n, int lane, double c, double s, double emr,
-                                       double emi) {
-  for (int e = lane; e < n; e += 64) {
-    double2 a = x[e], b = y[e];
-    // b' = e^{-i phi} b
-    double br = emr * b.x - emi * b.y, bi = emr * b.y + emi * b.x;
-    x[e] = make_double2(c * a.x - s * br, c * a.y - s * bi);
-    y[e] = make_double2(s * a.x + c * br, s * a.y + c * bi);
-  }
-}
-
-// One round of the circle schedule: pair i of round r is (np-1, r) for i = 0 and
-// ((r+i) mod (np-1), (r-i) mod (np-1)) otherwise; every pair meets once per sweep.
-__global__ __launch_bounds__(256) void svd_round_kernel(const SvdMat* __restrict__ mats, int nmats,
-                                                        int64_t total_pairs, int round, double tol,
-                                                        int32_t* __restrict__ counter) {
-  const int lane = threadIdx.x & 63;
-  const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (gw >= total_pairs) return;
-  const int j = find_mat(mats, nmats, gw);
-  const SvdMat m = mats[j];
-  const int i = (int)(gw - m.pair_base);
-  const int np = m.kpad;
-  if (round >= np - 1 || i >= np / 2) return;
-  int p, q;
+// Circle schedule on n (even) items: pair i of round r is (n-1, r) for i = 0 and
+// ((r+i) mod (n-1), (r-i) mod (n-1)) otherwise; every pair meets once in n-1 rounds.
+__device__ __forceinline__ void circle_pair(int n, int r, int i, int& p, int& q) {
   if (i == 0) {
-    p = np - 1;
-    q = round;
+    p = n - 1;
+    q = r;
   } else {
-    p = (round + i) % (np - 1);
-    q = (round - i + (np - 1)) % (np - 1);
+    p = (r + i) % (n - 1);
+    q = (r - i + (n - 1)) % (n - 1);
   }
   if (p > q) {
     int t = p;
     p = q;
     q = t;
   }
-  if (q >= m.k) return;
-  double2* gp = (double2*)m.G + (int64_t)p * m.ell;
-  double2* gq = (double2*)m.G + (int64_t)q * m.ell;
-  double a = 0, b = 0, gr = 0, gi = 0;
-  for (int e = lane; e < m.ell; e += 64) {
-    double2 x = gp[e], y = gq[e];
-    a += x.x * x.x + x.y * x.y;
-    b += y.x * y.x + y.y * y.y;
-    gr += x.x * y.x + x.y * y.y;  // conj(x) y
-    gi += x.x * y.y - x.y * y.x;
+}
+
+constexpr int SVD_PW = 2 * SVD_BLOCK;  // columns of a block pair
+
+// 1/sqrt(x) and 1/x for normal positive x: hardware estimate refined by two Newton steps
+// (each step doubles the number of correct bits of the estimate).
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(fma(-x, y, 1.0), y, y);
+  y = fma(fma(-x, y, 1.0), y, y);
+  return y;
+}
+
+// Rotation that makes columns p, q of a pair orthogonal, from a = |g_p|^2, b = |g_q|^2 and
+// gamma = g_p^H g_q: g_p' = c g_p - s e^{-i phi} g_q, g_q' = s g_p + c e^{-i phi} g_q with
+// gamma = |gamma| e^{i phi} (the smaller of the two angles that zero the overlap).  A pair is
+// rotated iff |gamma| > tol sqrt(a b) and |gamma| > thr sqrt(max(a, b)), tested on squares;
+// overlaps below 1e-145 in modulus count as zero.
+struct Rot {
+  double c, s, er, ei;  // (er, ei) = e^{-i phi}
+};
+
+__device__ __forceinline__ bool make_rot(double a, double b, double gr, double gi, double tol, double thr, Rot& R) {
+  const double g2 = gr * gr + gi * gi;
+  if (!(g2 > tol * tol * (a * b)) || !(g2 > thr * thr * fmax(a, b)) || !(g2 > 1e-290)) return false;
+  const double ri = rsq_nr(g2);  // 1 / |gamma|
+  const double zeta = 0.5 * (b - a) * ri;
+  const double az = fabs(zeta);
+  double t;
+  if (az > 1e100) {
+    t = 0.5 * rcp_nr(az);
+  } else {
+    const double q = 1.0 + az * az;
+    t = rcp_nr(az + q * rsq_nr(q));
   }
-  a = wave_sum(a);
-  b = wave_sum(b);
-  gr = wave_sum(gr);
-  gi = wave_sum(gi);
-  const double ag = sqrt(gr * gr + gi * gi);
-  if (!(ag > tol * sqrt(a * b)) || !(ag > m.thr * sqrt(fmax(a, b))) || ag == 0.0) return;
-  if (lane == 0) atomicAdd(counter, 1);
-  const double zeta = (b - a) / (2.0 * ag);
-  const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-  const double emr = gr / ag, emi = -gi / ag;  // e^{-i phi}
-  rotate(gp, gq, m.ell, lane, c, s, emr, emi);
-  rotate((double2*)m.V + (int64_t)p * m.k, (double2*)m.V + (int64_t)q * m.k, m.k, lane, c, s, emr, emi);
+  if (zeta < 0) t = -t;
+  R.c = rsq_nr(1.0 + t * t);
+  R.s = R.c * t;
+  R.er = gr * ri;
+  R.ei = -gi * ri;
+  return true;
+}
+
+// One round of the block one-sided Jacobi method.  The columns of every matrix are cut into
+// blocks of SVD_BLOCK; workgroup i of the round owns block pair i of the circle schedule over
+// the blocks, i.e. 16 columns P.  It forms the Gram matrix M = P^H P on the FP64 MFMA units,
+// runs one cyclic Jacobi sweep on M in LDS (M <- J^H M J and Q <- Q J for every pair whose
+// overlap exceeds the tolerance, with the same test and rotation as the scalar method) and,
+// if any pair was rotated, overwrites P by P Q and the matching 16 columns of V by V Q, again
+// on the MFMA units.  M is formed afresh from the columns at every visit, so a sweep without
+// rotations certifies the pairwise test on the columns.
+//
+// MFMA f64 16x16x4 lane layout: lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds
+// D[l/16 + 4e][l%16] in register e.  For the Gram matrix both operands are the element
+// P[4s + l/16][l%16] of the 4-row step s.  Every wave issues the loads of a whole batch of
+// steps (tiles) before its first MFMA, so a block pair's panel is in flight at once.
+constexpr int SVD_WAVES = 8;
+constexpr int SVD_GB = 16;  // Gram: 4-row steps per wave and batch
+constexpr int SVD_UB = 4;   // update: 16-row tiles per wave and batch
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(64 * SVD_WAVES) void svd_block_round_kernel(const SvdMat* __restrict__ mats, int nmats,
+                                                                         int round, double tol,
+                                                                         int32_t* __restrict__ counter) {
+  static_assert(SVD_PW == 16, "one 16 x 16 MFMA tile per block pair");
+  typedef double v4d __attribute__((ext_vector_type(4)));
+  __shared__ double2 Mp[SVD_WAVES][SVD_PW][SVD_PW + 1];  // per-wave partial Gram matrices
+  __shared__ double2 Ms[SVD_PW][SVD_PW + 1];
+  __shared__ double2 Qs[SVD_PW][SVD_PW + 1];
+  __shared__ int col[SVD_PW];
+  __shared__ int rotated;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int j = find_mat(mats, nmats, blockIdx.x);
+  const SvdMat m = mats[j];
+  const int i = (int)(blockIdx.x - m.pair_base);
+  if (round >= m.nblk - 1 || i >= m.nblk / 2) return;  // uniform over the workgroup
+  int bI, bJ;
+  circle_pair(m.nblk, round, i, bI, bJ);
+  if (t < SVD_PW) {
+    const int c = (t < SVD_BLOCK ? bI : bJ) * SVD_BLOCK + (t % SVD_BLOCK);
+    col[t] = c < m.k ? c : -1;
+  }
+  if (t == 0) rotated = 0;
+  __syncthreads();
+
+  // Gram matrix: wave w takes the 4-row steps w, w + SVD_WAVES, ...
+  {
+    const double2* G = (const double2*)m.G;
+    const int c = col[l16];
+    const int nsteps = (m.ell + 3) >> 2;
+    v4d r1 = {0, 0, 0, 0}, r2 = r1, i1 = r1, i2 = r1;
+    for (int s0 = wave; s0 < nsteps; s0 += SVD_WAVES * SVD_GB) {
+      double2 v[SVD_GB];
+#pragma unroll
+      for (int u = 0; u < SVD_GB; ++u) {
+        const int row = 4 * (s0 + SVD_WAVES * u) + lq;
+        v[u] = (c >= 0 && row < m.ell) ? G[(int64_t)c * m.ell + row] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < SVD_GB; ++u) {
+        r1 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u].x, v[u].x, r1, 0, 0, 0);
+        i1 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u].x, v[u].y, i1, 0, 0, 0);
+        r2 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u].y, v[u].y, r2, 0, 0, 0);
+        i2 = __builtin_amdgcn_mfma_f64_16x16x4f64(-v[u].y, v[u].x, i2, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Mp[wave][lq + 4 * e][l16] = make_double2(r1[e] + r2[e], i1[e] + i2[e]);
+  }
+  __syncthreads();
+  if (t < SVD_PW * SVD_PW) {
+    const int a = t >> 4, b = t & 15;
+    double sr = 0, si = 0;
+#pragma unroll
+    for (int w = 0; w < SVD_WAVES; ++w) {
+      sr += Mp[w][a][b].x;
+      si += Mp[w][a][b].y;
+    }
+    Ms[a][b] = make_double2(sr, a == b ? 0.0 : si);
+    Qs[a][b] = make_double2(a == b ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+
+  // one cyclic sweep on M by wave 0 (wave-synchronous LDS): lane l serves pair l / 8; the
+  // column step rotates rows l%8 and l%8 + 8 of M and Q, the row step columns l%8, l%8 + 8
+  if (wave == 0) {
+    const int pr = lane >> 3, sub = lane & 7;
+    bool any = false;
+    for (int r = 0; r < SVD_PW - 1; ++r) {
+      int p, q;
+      circle_pair(SVD_PW, r, pr, p, q);
+      Rot R;
+      const double2 g = Ms[p][q];
+      const bool rot = make_rot(Ms[p][p].x, Ms[q][q].x, g.x, g.y, tol, m.thr, R);
+      any |= rot;
+      wave_sync();
+      if (rot) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          double2(*X)[SVD_PW + 1] = u < 2 ? Ms : Qs;
+          const int x = sub + 8 * (u & 1);
+          const double2 a = X[x][p], b = X[x][q];
+          const double br = R.er * b.x - R.ei * b.y, bi = R.er * b.y + R.ei * b.x;  // e^{-i phi} b
+          X[x][p] = make_double2(R.c * a.x - R.s * br, R.c * a.y - R.s * bi);
+          X[x][q] = make_double2(R.s * a.x + R.c * br, R.s * a.y + R.c * bi);
+        }
+      }
+      wave_sync();
+      if (rot) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int y = sub + 8 * u;
+          const double2 a = Ms[p][y], b = Ms[q][y];
+          const double br = R.er * b.x + R.ei * b.y, bi = R.er * b.y - R.ei * b.x;  // e^{+i phi} b
+          Ms[p][y] = make_double2(R.c * a.x - R.s * br, R.c * a.y - R.s * bi);
+          Ms[q][y] = make_double2(R.s * a.x + R.c * br, R.s * a.y + R.c * bi);
+        }
+      }
+      wave_sync();
+    }
+    if (__any(any) && lane == 0) rotated = 1;
+  }
+  __syncthreads();
+  if (!rotated) return;  // uniform: read after the barrier
+  if (t == 0) atomicAdd(counter, 1);
+
+  // P <- P Q and V <- V Q in 16-row tiles, wave w taking tiles w, w + SVD_WAVES, ...; k-step
+  // s of a tile reads column 4s + l/16 at row l%16 (A operand) and keeps Q[4s + l/16][l%16]
+  double qr[4], qi[4];
+  int cin[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const double2 qv = Qs[4 * s + lq][l16];
+    qr[s] = qv.x;
+    qi[s] = qv.y;
+    cin[s] = col[4 * s + lq];
+  }
+  const int cout = col[l16];
+  for (int pass = 0; pass < 2; ++pass) {
+    double2* X = (double2*)(pass == 0 ? m.G : m.V);
+    const int len = pass == 0 ? m.ell : m.k;
+    const int ntiles = (len + 15) >> 4;
+    for (int t0 = wave; t0 < ntiles; t0 += SVD_WAVES * SVD_UB) {
+      double2 v[SVD_UB][4];
+#pragma unroll
+      for (int u = 0; u < SVD_UB; ++u) {
+        const int row = 16 * (t0 + SVD_WAVES * u) + l16;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          v[u][s] = (cin[s] >= 0 && row < len) ? X[(int64_t)cin[s] * len + row] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < SVD_UB; ++u) {
+        v4d ar = {0, 0, 0, 0}, ai = ar, br = ar, bi = ar;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          ar = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u][s].x, qr[s], ar, 0, 0, 0);
+          ai = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u][s].x, qi[s], ai, 0, 0, 0);
+          br = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u][s].y, -qi[s], br, 0, 0, 0);
+          bi = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u][s].y, qr[s], bi, 0, 0, 0);
+        }
+        const int tile = t0 + SVD_WAVES * u;
+        if (cout >= 0) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int row = 16 * tile + lq + 4 * e;
+            if (row < len) X[(int64_t)cout * len + row] = make_double2(ar[e] + br[e], ai[e] + bi[e]);
+          }
+        }
+      }
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void svd_norms_kernel(const SvdMat* __restrict__ mats, int nmats, int maxk,
@@ -163,9 +342,8 @@ void launch_svd_init(const SvdMat* mats, int nmats, void* stream) {
 void launch_svd_round(const SvdMat* mats, int nmats, int64_t total_pairs, int round, double tol, int32_t* counter,
                       void* stream) {
   if (nmats <= 0 || total_pairs <= 0) return;
-  int64_t blocks = (total_pairs + 3) / 4;
-  hipLaunchKernelGGL(svd_round_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, mats, nmats,
-                     total_pairs, round, tol, counter);
+  hipLaunchKernelGGL(svd_block_round_kernel, dim3((unsigned)total_pairs), dim3(64 * SVD_WAVES), 0, (hipStream_t)stream, mats,
+                     nmats, round, tol, counter);
   check(hipGetLastError(), "svd round launch");
 }
 

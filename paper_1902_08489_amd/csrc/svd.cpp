@@ -1,15 +1,19 @@
 // SVD truncation (Methods, "MPS" paragraph: keep the D largest singular values) with a
-// batched one-sided Jacobi SVD on the device, always in FP64.
+// QR-preconditioned batched block one-sided Jacobi SVD on the device, always in FP64.
 //
-// Each charge sector of a two-site tensor is a matrix M (R x C).  The smaller dimension is
-// orthogonalised: G = M (R >= C) or G = M^H (R < C), rotating column pairs of G and
-// accumulating the rotations in V until every pair is orthogonal to rounding; then
-// sigma_j = |g_j| and M = sum_j sigma_j ul_j vr_j^H with (ul, vr) = (g/sigma, v) or
-// (v, g/sigma).  Truncation: all sectors' sigma sorted together (value descending, then
-// sector in charge order, then index), at most Dmax kept and only those above
-// cutoff * sigma_max (never fewer than one); no renormalisation.
+// Each charge sector of a two-site tensor is a matrix M (R x C).  It is decomposed as G = M
+// or G = M^H, chosen so that the side of M that becomes the canonical site tensor is the
+// ell side of G: G = Q R (Householder), block Jacobi on X = R^H until every column pair is
+// orthogonal to rounding (X V = W), then G = (Q [V; 0]) Sigma (W Sigma^{-1})^H.  The ell-side
+// vectors Q [V; 0] are orthonormal to rounding, so the canonical tensor is exactly isometric
+// even for tiny kept singular values; the other side carries sigma.  Truncation: all
+// sectors' sigma sorted together (value descending, then sector in charge order, then index),
+// at most Dmax kept and only those above cutoff * sigma_max (never fewer than one); no
+// renormalisation.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <numeric>
 
 #include "engine.h"
@@ -19,100 +23,149 @@ namespace {
 
 struct SvdJob {
   int R = 0, C = 0;
-  bool tall = true;  // G = M (R >= C) else G = M^H
-  int ell = 0, k = 0;
-  int64_t goff = 0, voff = 0;
+  bool gm = true;         // G = M (ell side = rows of M) else G = M^H (ell side = columns of M)
+  int ell = 0, k = 0, n = 0;  // G is ell x k, n = min(ell, k) singular values
+  int64_t goff = 0, boff = 0, xoff = 0, voff = 0, toff = 0;
   std::vector<double> sigma;
 };
 
 struct SvdBatch {
   std::vector<SvdJob> jobs;
-  DevBuf G, V;
-  int64_t gsize = 0, vsize = 0;
+  DevBuf G, X, V, B, T;
+  int64_t gsize = 0, bsize = 0, xsize = 0, vsize = 0, tsize = 0;
 
-  void add(int R, int C) {
+  // row_side: the rows of M (left of the bond) become the canonical side, else its columns.
+  void add(int R, int C, bool row_side) {
     SvdJob j;
     j.R = R;
     j.C = C;
-    j.tall = R >= C;
-    j.ell = j.tall ? R : C;
-    j.k = j.tall ? C : R;
+    j.gm = row_side;
+    j.ell = j.gm ? R : C;
+    j.k = j.gm ? C : R;
+    j.n = std::min(j.ell, j.k);
     j.goff = gsize;
+    j.boff = bsize;
+    j.xoff = xsize;
     j.voff = vsize;
+    j.toff = tsize;
     gsize += (int64_t)j.ell * j.k;
-    vsize += (int64_t)j.k * j.k;
+    bsize += (int64_t)j.ell * j.n;
+    xsize += (int64_t)j.k * j.n;
+    vsize += (int64_t)j.n * j.n;
+    tsize += (int64_t)((j.n + QR_PANEL - 1) / QR_PANEL) * QR_PANEL * QR_PANEL;
     jobs.push_back(j);
   }
   void alloc() {
     G = DevBuf(std::max<int64_t>(gsize, 1) * sizeof(cplx));
+    B = DevBuf(std::max<int64_t>(bsize, 1) * sizeof(cplx));
+    X = DevBuf(std::max<int64_t>(xsize, 1) * sizeof(cplx));
     V = DevBuf(std::max<int64_t>(vsize, 1) * sizeof(cplx));
+    T = DevBuf(std::max<int64_t>(tsize, 1) * sizeof(cplx));
   }
-  cplx* g(int j) const { return G.c() + jobs[j].goff; }
-  cplx* v(int j) const { return V.c() + jobs[j].voff; }
+  cplx* in(int j) const { return G.c() + jobs[j].goff; }
+  // After run(): u(j) (ell x n) holds the ell-side singular vectors, w(j) (k x n) the k-side
+  // ones, both unit columns, G = u Sigma w^H.
+  cplx* u(int j) const { return B.c() + jobs[j].boff; }
+  cplx* w(int j) const { return X.c() + jobs[j].xoff; }
 
   // Copy a block of M (rows r0.., cols c0..) given as a row-major source with leading dim ld.
   void gather(CopyPlan& cp, int j, const cplx* src, int ld, int rows, int cols, int r0, int c0) const {
     const SvdJob& J = jobs[j];
-    if (J.tall)  // G[c][r] (column-major) = M[r][c]: dst rows = M cols
-      cp.add(src, 1, ld, g(j) + (int64_t)c0 * J.ell + r0, J.ell, cols, rows, 0);
+    if (J.gm)  // G[c][r] (column-major) = M[r][c]: dst rows = M cols
+      cp.add(src, 1, ld, in(j) + (int64_t)c0 * J.ell + r0, J.ell, cols, rows, 0);
     else  // G[r][c] = conj(M[r][c]) in G's column-major (ell = C) order: dst rows = M rows
-      cp.add(src, ld, 1, g(j) + (int64_t)r0 * J.ell + c0, J.ell, rows, cols, 1);
+      cp.add(src, ld, 1, in(j) + (int64_t)r0 * J.ell + c0, J.ell, rows, cols, 1);
+  }
+
+  // Column norms of the matrices described by mats into host memory (maxk per matrix).
+  static std::vector<double> norms(Ctx* ctx, const std::vector<SvdMat>& mats, int maxk) {
+    DevBuf sig(std::max<size_t>(1, mats.size() * (size_t)maxk) * sizeof(double));
+    std::vector<double> hs(mats.size() * (size_t)maxk);
+    Staging st;
+    const SvdMat* dm = st.put(ctx, mats);
+    launch_svd_norms(dm, (int)mats.size(), maxk, (double*)sig.p, ctx->stream);
+    dev_d2h(hs.data(), sig.p, hs.size() * sizeof(double), ctx->stream);
+    return hs;
   }
 
   void run(Ctx* ctx) {
     if (jobs.empty()) return;
-    std::vector<SvdMat> mats;
-    int64_t pairs = 0;
-    int maxk = 0, maxrounds = 0;
-    for (size_t j = 0; j < jobs.size(); ++j) {
-      SvdMat m;
-      m.G = g((int)j);
-      m.V = v((int)j);
-      m.ell = jobs[j].ell;
-      m.k = jobs[j].k;
-      m.kpad = m.k + (m.k & 1);
-      m.pair_base = (int32_t)pairs;
-      pairs += m.kpad / 2;
-      maxk = std::max(maxk, m.k);
-      maxrounds = std::max(maxrounds, m.kpad - 1);
-      mats.push_back(m);
+    const int nm = (int)jobs.size();
+    int maxk = 0, maxn = 0;
+    std::vector<QrMat> qm(nm);
+    std::vector<SvdMat> gmats(nm), xm(nm);
+    int cblocks = 0, pairs = 0, maxrounds = 0;
+    for (int j = 0; j < nm; ++j) {
+      const SvdJob& J = jobs[j];
+      maxk = std::max(maxk, J.k);
+      maxn = std::max(maxn, J.n);
+      QrMat& q = qm[j];
+      q.G = G.c() + J.goff;
+      q.B = B.c() + J.boff;
+      q.X = X.c() + J.xoff;
+      q.V = V.c() + J.voff;
+      q.T = T.c() + J.toff;
+      q.ell = J.ell;
+      q.k = J.k;
+      q.nsv = J.n;
+      q.cb_base = cblocks;
+      cblocks += (J.k + QR_PANEL - 1) / QR_PANEL;
+      gmats[j] = SvdMat{q.G, q.V, J.ell, J.k, 2, 0, 0.0};
+      const int nb = (J.n + SVD_BLOCK - 1) / SVD_BLOCK;
+      SvdMat& x = xm[j];
+      x.G = q.X;
+      x.V = q.V;
+      x.ell = J.k;
+      x.k = J.n;
+      x.nblk = std::max(2, nb + (nb & 1));
+      x.pair_base = pairs;
+      pairs += x.nblk / 2;
+      maxrounds = std::max(maxrounds, x.nblk - 1);
     }
-    // Rounding leaves every column with an absolute error of order eps |A|, so the
-    // overlap of columns p, q cannot be resolved below ~ eps |A| max(|g_p|, |g_q|):
-    // such pairs count as orthogonal (accuracy eps * sigma_max, as for LAPACK).
-    DevBuf sig(std::max<size_t>(1, mats.size() * (size_t)maxk) * sizeof(double));
-    std::vector<double> hs(mats.size() * (size_t)maxk);
+    // Rounding leaves every column with an absolute error of order eps |A|, so the overlap
+    // of columns p, q cannot be resolved below ~ eps |A| max(|g_p|, |g_q|): such pairs count
+    // as orthogonal (accuracy eps * sigma_max, as for LAPACK).  |X|_F = |G|_F.
     {
-      Staging st0;
-      const SvdMat* dm0 = st0.put(ctx, mats);
-      launch_svd_norms(dm0, (int)mats.size(), maxk, (double*)sig.p, ctx->stream);
-      dev_d2h(hs.data(), sig.p, hs.size() * sizeof(double), ctx->stream);
-    }
-    for (size_t j = 0; j < mats.size(); ++j) {
-      double f = 0;
-      for (int c = 0; c < mats[j].k; ++c) f += hs[j * maxk + c] * hs[j * maxk + c];
-      mats[j].thr = 8 * 2.220446049250313e-16 * std::sqrt(f);
+      std::vector<double> hs = norms(ctx, gmats, maxk);
+      for (int j = 0; j < nm; ++j) {
+        double f = 0;
+        for (int c = 0; c < jobs[j].k; ++c) f += hs[(size_t)j * maxk + c] * hs[(size_t)j * maxk + c];
+        xm[j].thr = 8 * 2.220446049250313e-16 * std::sqrt(f);
+      }
     }
     Staging st;
-    const SvdMat* dm = st.put(ctx, mats);
-    launch_svd_init(dm, (int)mats.size(), ctx->stream);
+    const QrMat* dq = st.put(ctx, qm);
+    for (int j0 = 0; j0 < maxn; j0 += QR_PANEL) {
+      launch_qr_panel(dq, nm, j0, ctx->stream);
+      launch_qr_apply(dq, nm, cblocks, j0, 0, ctx->stream);
+    }
+    launch_qr_rt(dq, nm, ctx->stream);
+    const SvdMat* dm = st.put(ctx, xm);
+    launch_svd_init(dm, nm, ctx->stream);
     DevBuf counter(sizeof(int32_t));
     const double tol = 1e-15;
     const int max_sweeps = 60;
-    bool converged = maxk <= 1;
-    for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+    bool converged = maxn <= 1;
+    int sweeps_done = 0;
+    for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep, ++sweeps_done) {
       dev_zero(counter.p, sizeof(int32_t), ctx->stream);
       for (int r = 0; r < maxrounds; ++r)
-        launch_svd_round(dm, (int)mats.size(), pairs, r, tol, (int32_t*)counter.p, ctx->stream);
+        launch_svd_round(dm, nm, pairs, r, tol, (int32_t*)counter.p, ctx->stream);
       int32_t rot = 0;
       dev_d2h(&rot, counter.p, sizeof(int32_t), ctx->stream);
       converged = rot == 0;
     }
     TDMPS_REQUIRE(converged, TDMPS_ERR_NUMERIC, "Jacobi SVD did not converge");
-    launch_svd_norms(dm, (int)mats.size(), maxk, (double*)sig.p, ctx->stream);
-    dev_d2h(hs.data(), sig.p, hs.size() * sizeof(double), ctx->stream);
-    for (size_t j = 0; j < jobs.size(); ++j)
-      jobs[j].sigma.assign(hs.begin() + j * maxk, hs.begin() + j * maxk + jobs[j].k);
+    if (std::getenv("TDMPS_SVD_STATS"))
+      std::fprintf(stderr, "svd: %d matrices, max n %d, %d rounds per sweep, %d sweeps\n", nm, maxn, maxrounds,
+                   sweeps_done);
+    std::vector<double> hs = norms(ctx, xm, maxn);
+    for (int j = 0; j < nm; ++j)
+      jobs[j].sigma.assign(hs.begin() + (size_t)j * maxn, hs.begin() + (size_t)j * maxn + jobs[j].n);
+    const double* dsig = st.put(ctx, hs);
+    launch_qr_finish(dq, nm, dsig, maxn, ctx->stream);
+    for (int j0 = (maxn - 1) / QR_PANEL * QR_PANEL; j0 >= 0; j0 -= QR_PANEL)
+      launch_qr_apply(dq, nm, cblocks, j0, 1, ctx->stream);
   }
 };
 
@@ -129,7 +182,7 @@ std::vector<Kept> select(const SvdBatch& b, int Dmax, double cutoff, double* dis
   };
   std::vector<C> all;
   for (size_t j = 0; j < b.jobs.size(); ++j)
-    for (int i = 0; i < b.jobs[j].k; ++i) all.push_back({b.jobs[j].sigma[i], (int)j, i});
+    for (int i = 0; i < b.jobs[j].n; ++i) all.push_back({b.jobs[j].sigma[i], (int)j, i});
   std::sort(all.begin(), all.end(), [](const C& x, const C& y) {
     if (x.s != y.s) return x.s > y.s;
     if (x.job != y.job) return x.job < y.job;
@@ -153,6 +206,12 @@ std::vector<Kept> select(const SvdBatch& b, int Dmax, double cutoff, double* dis
 
 TruncResult split_theta(Contractor& C, const cplx* theta, const TwoLayout& tl, Mps* m, int i, int Dmax, double cutoff,
                         bool move_right) {
+  const double t0 = wall_seconds();
+  struct Acc {
+    Contractor& C;
+    double t0;
+    ~Acc() { C.t_svd += wall_seconds() - t0; }
+  } acc_{C, t0};
   const Bond& l = m->bond[i];
   const Bond& r = m->bond[i + 2];
   // middle charges and their row / column groups
@@ -194,7 +253,7 @@ TruncResult split_theta(Contractor& C, const cplx* theta, const TwoLayout& tl, M
     int R = 0, Cc = 0;
     for (auto& x : rowg[k]) R += l.dim[x.first];
     for (auto& x : colg[k]) Cc += r.dim[x.second];
-    b.add(R, Cc);
+    b.add(R, Cc, move_right);
   }
   b.alloc();
   {
@@ -229,7 +288,7 @@ TruncResult split_theta(Contractor& C, const cplx* theta, const TwoLayout& tl, M
   DevBuf A(la.size * sizeof(cplx)), B(lb.size * sizeof(cplx));
   // per kept sector: index and scale arrays
   std::vector<int32_t> idx;
-  std::vector<double> one_s, sig_s, inv_s;
+  std::vector<double> one_s, sig_s;
   std::vector<int64_t> base(mid.nsec());
   for (int ms = 0; ms < mid.nsec(); ++ms) {
     const auto& kc = kept[job_of_sec[ms]].cols;
@@ -239,43 +298,37 @@ TruncResult split_theta(Contractor& C, const cplx* theta, const TwoLayout& tl, M
       idx.push_back(c);
       one_s.push_back(1.0);
       sig_s.push_back(sv[c]);
-      inv_s.push_back(sv[c] > 0 ? 1.0 / sv[c] : 0.0);
     }
   }
   Staging st;
   const int32_t* didx = st.put(C.ctx, idx);
   const double* d1 = st.put(C.ctx, one_s);
   const double* ds = st.put(C.ctx, sig_s);
-  const double* di = st.put(C.ctx, inv_s);
   CopyPlan cp;
   for (int ms = 0; ms < mid.nsec(); ++ms) {
     int k = job_of_sec[ms];
     const SvdJob& J = b.jobs[k];
     int nk = mid.dim[ms];
     const int32_t* ix = didx + base[ms];
-    // left site blocks (s, s1) -> ms: ul * (sigma if !move_right)
+    // left site blocks (s, s1) -> ms: ul (times sigma when moving left)
+    const double* lsc = move_right ? d1 + base[ms] : ds + base[ms];
     for (size_t a = 0; a < rowg[k].size(); ++a) {
       int s = rowg[k][a].first, s1 = rowg[k][a].second;
       cplx* dst = A.c() + la.panel_off[s] + la.col[s][s1];
-      if (J.tall) {  // ul = g / sigma
-        const double* sc = move_right ? di + base[ms] : d1 + base[ms];
-        cp.add(b.g(k) + rowoff[k][a], 1, J.ell, dst, la.width[s], l.dim[s], nk, 0, nullptr, ix, nullptr, sc);
-      } else {  // ul = v
-        const double* sc = move_right ? d1 + base[ms] : ds + base[ms];
-        cp.add(b.v(k) + rowoff[k][a], 1, J.k, dst, la.width[s], l.dim[s], nk, 0, nullptr, ix, nullptr, sc);
-      }
+      if (J.gm)  // ul = u
+        cp.add(b.u(k) + rowoff[k][a], 1, J.ell, dst, la.width[s], l.dim[s], nk, 0, nullptr, ix, nullptr, lsc);
+      else  // ul = w
+        cp.add(b.w(k) + rowoff[k][a], 1, J.k, dst, la.width[s], l.dim[s], nk, 0, nullptr, ix, nullptr, lsc);
     }
-    // right site blocks ms -> (s2, t): (sigma if move_right) * vr^H
+    // right site blocks ms -> (s2, t): (sigma when moving right) vr^H
+    const double* rsc = move_right ? ds + base[ms] : d1 + base[ms];
     for (size_t c = 0; c < colg[k].size(); ++c) {
       int s2 = colg[k][c].first, t = colg[k][c].second;
       cplx* dst = B.c() + lb.panel_off[ms] + lb.col[ms][s2];
-      if (J.tall) {  // vr = v
-        const double* sc = move_right ? ds + base[ms] : d1 + base[ms];
-        cp.add(b.v(k) + coloff[k][c], J.k, 1, dst, lb.width[ms], nk, r.dim[t], 1, ix, nullptr, sc, nullptr);
-      } else {  // vr = g / sigma
-        const double* sc = move_right ? d1 + base[ms] : di + base[ms];
-        cp.add(b.g(k) + coloff[k][c], J.ell, 1, dst, lb.width[ms], nk, r.dim[t], 1, ix, nullptr, sc, nullptr);
-      }
+      if (J.gm)  // vr = w
+        cp.add(b.w(k) + coloff[k][c], J.k, 1, dst, lb.width[ms], nk, r.dim[t], 1, ix, nullptr, rsc, nullptr);
+      else  // vr = u
+        cp.add(b.u(k) + coloff[k][c], J.ell, 1, dst, lb.width[ms], nk, r.dim[t], 1, ix, nullptr, rsc, nullptr);
     }
   }
   cp.run(C.ctx);
@@ -297,7 +350,7 @@ void right_canonicalize(Contractor& C, Mps* m, double cutoff) {
     for (int s = 0; s < l.nsec(); ++s)
       if (lay.width[s] > 0) {
         job_of[s] = (int)b.jobs.size();
-        b.add(l.dim[s], lay.width[s]);
+        b.add(l.dim[s], lay.width[s], false);
       }
     b.alloc();
     {
@@ -322,7 +375,7 @@ void right_canonicalize(Contractor& C, Mps* m, double cutoff) {
     pl.build(m->bond[i - 1], nb);
     DevBuf A(nl.size * sizeof(cplx)), P(pl.size * sizeof(cplx));
     std::vector<int32_t> idx;
-    std::vector<double> ones, sig, inv;
+    std::vector<double> ones, sig;
     std::vector<int64_t> base;
     for (size_t ns = 0; ns < sec_of.size(); ++ns) {
       int j = job_of[sec_of[ns]];
@@ -332,14 +385,12 @@ void right_canonicalize(Contractor& C, Mps* m, double cutoff) {
         ones.push_back(1.0);
         double sv = b.jobs[j].sigma[c];
         sig.push_back(sv);
-        inv.push_back(sv > 0 ? 1.0 / sv : 0.0);
       }
     }
     Staging st;
     const int32_t* didx = st.put(C.ctx, idx);
     const double* d1 = st.put(C.ctx, ones);
     const double* ds = st.put(C.ctx, sig);
-    const double* di = st.put(C.ctx, inv);
     // new site i = vr^H (rows = kept), and US = ul * sigma per sector (D_s x k)
     int64_t us_size = 0;
     std::vector<int64_t> us_off;
@@ -355,16 +406,11 @@ void right_canonicalize(Contractor& C, Mps* m, double cutoff) {
       const SvdJob& J = b.jobs[j];
       int nk = nb.dim[ns];
       const int32_t* ix = didx + base[ns];
-      // vr^H into the new panel (width identical to the old one: same right bond)
+      // vr^H into the new panel (width identical to the old one: same right bond); G = M^H so
+      // vr = u (isometric) and ul = w
       cplx* dst = A.c() + nl.panel_off[ns];
-      if (J.tall)
-        cp.add(b.v(j), J.k, 1, dst, nl.width[ns], nk, lay.width[s], 1, ix, nullptr, d1 + base[ns], nullptr);
-      else
-        cp.add(b.g(j), J.ell, 1, dst, nl.width[ns], nk, lay.width[s], 1, ix, nullptr, di + base[ns], nullptr);
-      if (J.tall)
-        cp.add(b.g(j), 1, J.ell, US.c() + us_off[ns], nk, l.dim[s], nk, 0, nullptr, ix, nullptr, d1 + base[ns]);
-      else
-        cp.add(b.v(j), 1, J.k, US.c() + us_off[ns], nk, l.dim[s], nk, 0, nullptr, ix, nullptr, ds + base[ns]);
+      cp.add(b.u(j), J.ell, 1, dst, nl.width[ns], nk, lay.width[s], 1, ix, nullptr, d1 + base[ns], nullptr);
+      cp.add(b.w(j), 1, J.k, US.c() + us_off[ns], nk, l.dim[s], nk, 0, nullptr, ix, nullptr, ds + base[ns]);
     }
     cp.run(C.ctx);
     // site i-1: A_{i-1}[a, n, s] (US)_s

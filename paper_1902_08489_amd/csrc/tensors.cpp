@@ -1,10 +1,15 @@
 // Block-sparse layouts, device buffers, task plans and basic state constructors.
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 
 #include "engine.h"
 
 namespace tdmps {
+
+double wall_seconds() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 // ---------------------------------------------------------------- device buffers
 DevBuf::DevBuf(size_t b) : bytes(b) {
