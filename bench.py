@@ -154,10 +154,16 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         cnt = ctx.counters()
+        tf = lambda f, t: f / max(t, 1e-9) / 1e12
         krylov = {"steps_per_s": args.krylov / dt, "s_per_step": dt / args.krylov, "m": args.krylov_m,
-                  "sweeps_per_fit": 1, "phase_seconds_last_step": {"heff": cnt[2], "env": cnt[3], "svd": cnt[4],
-                                                                    "premix": cnt[5], "sandwich": cnt[6]},
-                  "heff_alg_tflops_in_step": cnt[0] / max(cnt[2], 1e-9) / 1e12}
+                  "sweeps_per_fit": 1,
+                  "phase_seconds_last_step": {"heff": cnt[2], "env": cnt[3], "svd": cnt[4], "svd_qr": cnt[15],
+                                              "premix": cnt[5], "sandwich_total": cnt[6]},
+                  "counts_last_step": {"heff": int(cnt[12]), "env_updates": int(cnt[13]), "svd": int(cnt[11]),
+                                       "sandwiches": int(cnt[14]), "jacobi_sweeps": int(cnt[9]),
+                                       "jacobi_rounds": int(cnt[10])},
+                  "tflops_last_step": {"heff_algorithmic": tf(cnt[0], cnt[2]), "heff_executed": tf(cnt[1], cnt[2]),
+                                       "env_executed": tf(cnt[7], cnt[3]), "premix_executed": tf(cnt[8], cnt[5])}}
 
     line = {
         "metric": "H_eff*theta TFLOP/s + Krylov steps/s @L=24 D=1024, mixed vs FP64",

@@ -93,12 +93,18 @@ const char* tdmps_last_error(void);
  * stream) or a borrowed hipStream_t that must outlive the context. */
 tdmps_status tdmps_ctx_create(int32_t device, void* hip_stream, tdmps_ctx* out);
 tdmps_status tdmps_ctx_destroy(tdmps_ctx ctx);
-/* Counters of the last operation (fit, time step or expectation value):
- * out[0] = algorithmic flops of the H_eff contractions, out[1] = executed H_eff flops,
- * out[2..6] = wall seconds spent in H_eff, environment updates, SVD truncation, premix
- * and sandwiches (sandwich time includes its own environment updates), out[7] = executed
- * environment-update flops.  After tdmps_heff_apply planning, out[0..7] describe the plan. */
-tdmps_status tdmps_ctx_counters(tdmps_ctx ctx, double* out8);
+/* Counters of the last operation (fit, time step or expectation value), TDMPS_NCOUNTERS
+ * doubles: out[0] = algorithmic flops of the H_eff contractions, out[1] = executed H_eff flops,
+ * out[2..6] = wall seconds spent in H_eff, environment updates, SVD truncation (QR included),
+ * premix and sandwiches (sandwich time includes its own environment updates and premix),
+ * out[7] = executed environment-update flops, out[8] = executed premix flops, out[9] / out[10]
+ * = Jacobi sweeps / rounds summed over the SVDs, out[11..14] = number of SVD truncations,
+ * H_eff applications, environment updates and sandwiches, out[15] = seconds in the QR
+ * preconditioning.  After tdmps_heff_apply planning, out[0..7] describe the plan instead:
+ * algorithmic flops, executed flops of the two stages, bytes of the intermediate, task and
+ * segment counts of the two stages. */
+#define TDMPS_NCOUNTERS 16
+tdmps_status tdmps_ctx_counters(tdmps_ctx ctx, double* out16);
 tdmps_status tdmps_ctx_reset_counters(tdmps_ctx ctx);
 
 /* ---------------------------------------------------------------- Hamiltonian MPO

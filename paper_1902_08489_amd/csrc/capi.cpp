@@ -44,6 +44,14 @@ void publish(Ctx* ctx, const Contractor& C) {
   ctx->counters[5] = C.t_mix;
   ctx->counters[6] = C.t_sandwich;
   ctx->counters[7] = C.env_flops;
+  ctx->counters[8] = C.mix_flops;
+  ctx->counters[9] = C.svd_sweeps;
+  ctx->counters[10] = C.svd_rounds;
+  ctx->counters[11] = C.n_svd;
+  ctx->counters[12] = C.n_heff;
+  ctx->counters[13] = C.n_env;
+  ctx->counters[14] = C.n_sandwich;
+  ctx->counters[15] = C.t_qr;
 }
 
 void check_prm(const tdmps_fit_params* p) {
@@ -95,10 +103,10 @@ extern "C" tdmps_status tdmps_ctx_destroy(tdmps_ctx ctx) {
   });
 }
 
-extern "C" tdmps_status tdmps_ctx_counters(tdmps_ctx ctx, double* out8) {
+extern "C" tdmps_status tdmps_ctx_counters(tdmps_ctx ctx, double* out16) {
   return guard([&] {
-    TDMPS_REQUIRE(ctx && out8, TDMPS_ERR_ARG, "NULL argument");
-    for (int i = 0; i < 8; ++i) out8[i] = ctx->counters[i];
+    TDMPS_REQUIRE(ctx && out16, TDMPS_ERR_ARG, "NULL argument");
+    for (int i = 0; i < TDMPS_NCOUNTERS; ++i) out16[i] = ctx->counters[i];
   });
 }
 

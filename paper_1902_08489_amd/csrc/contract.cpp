@@ -13,6 +13,8 @@
 // GEMM over the channel index.  Consecutive middle channels with the same structure form
 // "runs" whose blocks are stacked, so each block product is one batched GEMM over a run.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <tuple>
@@ -311,6 +313,7 @@ Env env_left_update(Contractor& C, const SideOps& ops, const Mps*, const cplx* b
   p2.run(C.ctx, C.precision);
   C.env_flops += p1.flops + p2.flops;
   C.t_env += wall_seconds() - t0;
+  C.n_env += 1;
   return out;
 }
 
@@ -408,6 +411,7 @@ Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, co
   p2.run(C.ctx, C.precision);
   C.env_flops += p1.flops + p2.flops;
   C.t_env += wall_seconds() - t0;
+  C.n_env += 1;
   return out;
 }
 
@@ -427,6 +431,7 @@ void heff_apply(Contractor& C, const SideOps& lops, const SideOps& rops, const c
   C.heff_flops += plan->p1.flops + plan->p2.flops;
   if (alg_flops) *alg_flops = plan->alg_flops;
   C.t_heff += wall_seconds() - t0;
+  C.n_heff += 1;
 }
 
 std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const SideOps& rops, const cplx* theta_in,
@@ -621,6 +626,7 @@ cplx sandwich(Contractor& C, const MpoHost& O, const Mps* bra, const Mps* ket) {
     double t0;
     ~Acc() { C.t_sandwich += wall_seconds() - t0; }
   } acc_{C, t0};
+  C.n_sandwich += 1;
   TDMPS_REQUIRE(bra->L == ket->L && bra->L == O.L, TDMPS_ERR_ARG, "length mismatch");
   TDMPS_REQUIRE(bra->total == ket->total, TDMPS_ERR_SECTOR, "bra and ket have different total charge");
   Env E = env_left_boundary(C.ctx, bra->bond[0], ket->bond[0]);

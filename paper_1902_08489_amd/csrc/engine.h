@@ -104,7 +104,7 @@ struct tdmps_ctx_s {
   void* stream = nullptr;
   bool own_stream = false;
   void* ev[2] = {nullptr, nullptr};
-  double counters[8] = {0};
+  double counters[TDMPS_NCOUNTERS] = {0};
   bool timing = false;
 };
 
@@ -184,12 +184,12 @@ struct GemmPlan {
   void add_seg(const cplx* A, int64_t bsA, int64_t rsA, int lda, int opA, const cplx* B, int64_t bsB, int64_t rsB,
                int ldb, int opB, int k, int nred, cplx alpha);
   // device copies of the task lists (finalize) and asynchronous launch
-  static constexpr int NCFG = 3;
+  static constexpr int NCFG = GEMM_NCFG;
   DevBuf dsegs, dtasks[NCFG], dtile[NCFG], wspace, dred;
   std::vector<int64_t> red_base;
   int nred_tasks = 0;
-  int ntask[NCFG] = {0, 0, 0};
-  int64_t ntiles[NCFG] = {0, 0, 0};
+  int ntask[NCFG] = {};
+  int64_t ntiles[NCFG] = {};
   bool final_ = false;
   void finalize(Ctx* ctx);
   void launch(Ctx* ctx, int precision);
@@ -225,7 +225,8 @@ struct Contractor {
   double heff_flops = 0, env_flops = 0, mix_flops = 0;
   double heff_alg_flops = 0;
   // wall-clock seconds per phase (every phase ends with a stream synchronisation)
-  double t_heff = 0, t_env = 0, t_mix = 0, t_svd = 0, t_sandwich = 0;
+  double t_heff = 0, t_env = 0, t_mix = 0, t_svd = 0, t_sandwich = 0, t_qr = 0;
+  double svd_sweeps = 0, svd_rounds = 0, n_svd = 0, n_heff = 0, n_env = 0, n_sandwich = 0;
 };
 
 double wall_seconds();

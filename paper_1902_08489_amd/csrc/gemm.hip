@@ -37,44 +37,81 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Iteration over the flattened (segment, channel, k-chunk) steps of one task.
-struct StepIt {
-  int s, r, k0;
+// Position in the flattened (segment, channel, k-chunk) steps of one task.  The segment
+// descriptor is read only when the cursor enters a new segment; a k step only moves k0.
+struct Cursor {
+  const GemmSeg* segs;
+  int s, se, r, k0, K, nred;
+  int64_t lda, ldb, rsA, rsB;
+  const double2* A;  // operands of channel r of the current segment
+  const double2* B;
+  double2 alpha;
+  bool tA, cA, tB, cB;
+
+  __device__ __forceinline__ bool open(int64_t bidx) {
+    for (; s < se; ++s) {
+      const GemmSeg& S = segs[s];
+      if (S.k <= 0 || S.nred <= 0) continue;
+      K = S.k;
+      nred = S.nred;
+      lda = S.lda;
+      ldb = S.ldb;
+      rsA = S.rsA;
+      rsB = S.rsB;
+      A = (const double2*)S.A + bidx * S.bsA;
+      B = (const double2*)S.B + bidx * S.bsB;
+      alpha = make_double2(S.alpha.x, S.alpha.y);
+      tA = S.opA == OP_T || S.opA == OP_C;
+      cA = S.opA == OP_C || S.opA == OP_J;
+      tB = S.opB == OP_T || S.opB == OP_C;
+      cB = S.opB == OP_C || S.opB == OP_J;
+      r = 0;
+      k0 = 0;
+      return true;
+    }
+    return false;
+  }
+  __device__ __forceinline__ bool advance(int64_t bidx, int bk) {
+    k0 += bk;
+    if (k0 < K) return true;
+    k0 = 0;
+    if (++r < nred) {
+      A += rsA;
+      B += rsB;
+      return true;
+    }
+    ++s;
+    return open(bidx);
+  }
 };
 
 template <int BM, int BN, int BK>
 struct Stage {
-  // per-thread prefetch registers: BM*BK/256 A elements and BK*BN/256 B elements
-  static constexpr int NA = BM * BK / 256;
-  static constexpr int NB = BK * BN / 256;
+  // per-thread prefetch registers: ceil(BM*BK/256) A elements and ceil(BK*BN/256) B elements
+  static constexpr int NA = (BM * BK + 255) / 256;
+  static constexpr int NB = (BK * BN + 255) / 256;
+  static constexpr bool FULLA = BM * BK % 256 == 0;
+  static constexpr bool FULLB = BK * BN % 256 == 0;
   double2 ra[NA], rb[NB];
 
-  __device__ __forceinline__ void load(const GemmSeg& S, const GemmTask& T, int bidx, int r, int k0, int m0, int n0,
-                                       int tid) {
-    const bool conjA = S.opA == OP_C || S.opA == OP_J;
-    const bool transA = S.opA == OP_T || S.opA == OP_C;
-    const bool conjB = S.opB == OP_C || S.opB == OP_J;
-    const bool transB = S.opB == OP_T || S.opB == OP_C;
-    const double2* A = (const double2*)S.A + bidx * S.bsA + r * S.rsA;
-    const double2* B = (const double2*)S.B + bidx * S.bsB + r * S.rsB;
-    const double2 alpha = make_double2(S.alpha.x, S.alpha.y);
+  __device__ __forceinline__ void load(const Cursor& c, const GemmTask& T, int m0, int n0, int tid) {
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
       const int e = tid + q * 256;
       int rr, kk;
-      if (!transA) {
+      if (!c.tA) {
         rr = e / BK;
         kk = e - rr * BK;
       } else {
         kk = e / BM;
         rr = e - kk * BM;
       }
-      const int gr = m0 + rr, gk = k0 + kk;
+      const int gr = m0 + rr, gk = c.k0 + kk;
       double2 v = make_double2(0.0, 0.0);
-      if (gr < T.m && gk < S.k) {
-        v = transA ? A[(int64_t)gk * S.lda + gr] : A[(int64_t)gr * S.lda + gk];
-        if (conjA) v.y = -v.y;
-        v = cmul(v, alpha);
+      if ((FULLA || e < BM * BK) && gr < T.m && gk < c.K) {
+        v = c.tA ? c.A[(int64_t)gk * c.lda + gr] : c.A[(int64_t)gr * c.lda + gk];
+        if (c.cA) v.y = -v.y;
+        v = cmul(v, c.alpha);
       }
       ra[q] = v;
     }
@@ -82,64 +119,23 @@ struct Stage {
     for (int q = 0; q < NB; ++q) {
       const int e = tid + q * 256;
       int kk, cc;
-      if (!transB) {
+      if (!c.tB) {
         kk = e / BN;
         cc = e - kk * BN;
       } else {
         cc = e / BK;
         kk = e - cc * BK;
       }
-      const int gk = k0 + kk, gc = n0 + cc;
+      const int gk = c.k0 + kk, gc = n0 + cc;
       double2 v = make_double2(0.0, 0.0);
-      if (gk < S.k && gc < T.n) {
-        v = transB ? B[(int64_t)gc * S.ldb + gk] : B[(int64_t)gk * S.ldb + gc];
-        if (conjB) v.y = -v.y;
+      if ((FULLB || e < BK * BN) && gk < c.K && gc < T.n) {
+        v = c.tB ? c.B[(int64_t)gc * c.ldb + gk] : c.B[(int64_t)gk * c.ldb + gc];
+        if (c.cB) v.y = -v.y;
       }
       rb[q] = v;
     }
   }
-
-  __device__ __forceinline__ void store(double2 (*As)[BK + 1], double2 (*Bs)[BN + 1], const GemmSeg& S, int tid) {
-    const bool transA = S.opA == OP_T || S.opA == OP_C;
-    const bool transB = S.opB == OP_T || S.opB == OP_C;
-#pragma unroll
-    for (int q = 0; q < NA; ++q) {
-      const int e = tid + q * 256;
-      int rr, kk;
-      if (!transA) {
-        rr = e / BK;
-        kk = e - rr * BK;
-      } else {
-        kk = e / BM;
-        rr = e - kk * BM;
-      }
-      As[rr][kk] = ra[q];
-    }
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int e = tid + q * 256;
-      int kk, cc;
-      if (!transB) {
-        kk = e / BN;
-        cc = e - kk * BN;
-      } else {
-        cc = e / BK;
-        kk = e - cc * BK;
-      }
-      Bs[kk][cc] = rb[q];
-    }
-  }
 };
-
-__device__ __forceinline__ bool next_step(const GemmSeg* __restrict__ segs, const GemmTask& T, StepIt& it, int BK) {
-  it.k0 += BK;
-  const GemmSeg& S = segs[it.s];
-  if (it.k0 < S.k) return true;
-  it.k0 = 0;
-  if (++it.r < S.nred) return true;
-  it.r = 0;
-  return ++it.s < T.seg0 + T.nseg;
-}
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
@@ -153,15 +149,22 @@ enum { P64 = 0, P32 = 1, PBF3 = 2 };
 
 template <int BM, int BN, int PREC>
 struct Smem;
+// FP64 / FP32: operands are kept realified in LDS so that every MFMA operand is one plain
+// LDS read: A' rows hold (Re, Im) interleaved along k (the complex row itself), B' holds the
+// 2 x 2 real block [[Re, Im], [-Im, Re]] of every complex element (row = realified k,
+// column = realified n).  Row paddings put the B' rows read by one instruction (realified k
+// = lane / 16) on distinct LDS banks: row strides of 16 (mod 32) doubles, 16 (mod 64) floats.
+constexpr int bpad64(int bn) { return ((16 - 2 * bn) % 32 + 32) % 32; }
+constexpr int bpad32(int bn) { return ((16 - 2 * bn) % 64 + 64) % 64; }
 template <int BM, int BN>
 struct Smem<BM, BN, P64> {
-  double2 A[BM][9];
-  double2 B[8][BN + 1];
+  double A[BM][2 * 8 + 2];
+  double B[2 * 8][2 * BN + bpad64(BN)];
 };
 template <int BM, int BN>
 struct Smem<BM, BN, P32> {
-  float2 A[BM][17];
-  float2 B[16][BN + 1];
+  float A[BM][2 * 16 + 4];
+  float B[2 * 16][2 * BN + bpad32(BN)];
 };
 template <int BM, int BN>
 struct Smem<BM, BN, PBF3> {
@@ -214,21 +217,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
   Stage<BM, BN, BK> st;
-  StepIt it{T.seg0, 0, 0};
-  bool have = T.nseg > 0;
-  while (have && (segs[it.s].k <= 0 || segs[it.s].nred <= 0)) {
-    if (++it.s >= T.seg0 + T.nseg) have = false;
-  }
-  if (have) st.load(segs[it.s], T, bidx, it.r, it.k0, m0, n0, tid);
+  Cursor cur;
+  cur.segs = segs;
+  cur.s = T.seg0;
+  cur.se = T.seg0 + T.nseg;
+  bool have = cur.open(bidx);
+  if (have) st.load(cur, T, m0, n0, tid);
   while (have) {
     // registers -> LDS in the precision's layout
     {
-      const GemmSeg& S = segs[it.s];
-      const bool transA = S.opA == OP_T || S.opA == OP_C;
-      const bool transB = S.opB == OP_T || S.opB == OP_C;
+      const bool transA = cur.tA;
+      const bool transB = cur.tB;
 #pragma unroll
       for (int q = 0; q < Stage<BM, BN, BK>::NA; ++q) {
         const int e = tid + q * 256;
+        if (!Stage<BM, BN, BK>::FULLA && e >= BM * BK) continue;
         int rr, kk;
         if (!transA) {
           rr = e / BK;
@@ -239,9 +242,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         }
         const double2 v = st.ra[q];
         if constexpr (PREC == P64) {
-          sm.A[rr][kk] = v;
+          *(double2*)&sm.A[rr][2 * kk] = v;
         } else if constexpr (PREC == P32) {
-          sm.A[rr][kk] = make_float2((float)v.x, (float)v.y);
+          *(float2*)&sm.A[rr][2 * kk] = make_float2((float)v.x, (float)v.y);
         } else {
           split_bf16(v.x, sm.Ah[rr][2 * kk], sm.Al[rr][2 * kk]);
           split_bf16(v.y, sm.Ah[rr][2 * kk + 1], sm.Al[rr][2 * kk + 1]);
@@ -250,6 +253,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 #pragma unroll
       for (int q = 0; q < Stage<BM, BN, BK>::NB; ++q) {
         const int e = tid + q * 256;
+        if (!Stage<BM, BN, BK>::FULLB && e >= BK * BN) continue;
         int kk, cc;
         if (!transB) {
           kk = e / BN;
@@ -260,9 +264,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         }
         const double2 v = st.rb[q];
         if constexpr (PREC == P64) {
-          sm.B[kk][cc] = v;
+          *(double2*)&sm.B[2 * kk][2 * cc] = v;
+          *(double2*)&sm.B[2 * kk + 1][2 * cc] = make_double2(-v.y, v.x);
         } else if constexpr (PREC == P32) {
-          sm.B[kk][cc] = make_float2((float)v.x, (float)v.y);
+          const float re = (float)v.x, im = (float)v.y;
+          *(float2*)&sm.B[2 * kk][2 * cc] = make_float2(re, im);
+          *(float2*)&sm.B[2 * kk + 1][2 * cc] = make_float2(-im, re);
         } else {
           // B' = [[Re, Im], [-Im, Re]] per complex element, stored transposed (column-major)
           __bf16 rh, rl, ih, il, nh, nl;
@@ -281,14 +288,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
       }
     }
     __syncthreads();
-    StepIt nx = it;
-    bool more = next_step(segs, T, nx, BK);
-    while (more && (segs[nx.s].k <= 0 || segs[nx.s].nred <= 0)) {
-      nx.k0 = 0;
-      nx.r = 0;
-      more = ++nx.s < T.seg0 + T.nseg;
-    }
-    if (more) st.load(segs[nx.s], T, bidx, nx.r, nx.k0, m0, n0, tid);
+    Cursor nx = cur;
+    const bool more = nx.advance(bidx, BK);
+    if (more) st.load(nx, T, m0, n0, tid);
     if constexpr (PREC == PBF3) {
       bf8 ah[TM], al[TM];
 #pragma unroll
@@ -312,21 +314,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 #pragma unroll
       for (int kr = 0; kr < 2 * BK; kr += 4) {
         const int kreal = kr + lq;
-        const int kc = kreal >> 1, kp = kreal & 1;
         typedef typename std::conditional<PREC == P64, double, float>::type r_t;
         r_t a[TM], bb[TN];
 #pragma unroll
-        for (int i = 0; i < TM; ++i) {
-          const auto av = sm.A[wm + i * 16 + l16][kc];
-          a[i] = kp ? av.y : av.x;
-        }
+        for (int i = 0; i < TM; ++i) a[i] = sm.A[wm + i * 16 + l16][kreal];
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          const int rc = 2 * wn + j * 16 + l16;
-          const auto bv = sm.B[kc][rc >> 1];
-          const int cp = rc & 1;
-          bb[j] = kp == 0 ? (cp == 0 ? bv.x : bv.y) : (cp == 0 ? -bv.y : bv.x);
-        }
+        for (int j = 0; j < TN; ++j) bb[j] = sm.B[kreal][2 * wn + j * 16 + l16];
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -339,7 +332,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
       }
     }
     __syncthreads();
-    it = nx;
+    cur = nx;
     have = more;
   }
   // Epilogue.  Output lane layouts on gfx950 (read off the hardware): register e of lane l
@@ -405,8 +398,14 @@ void launch_reduce(const ReduceTask* tasks, int ntasks, void* stream) {
   check(hipGetLastError(), "reduce launch");
 }
 
-int gemm_tile_m(int cfg) { return cfg == 0 ? 64 : (cfg == 1 ? 32 : 128); }
-int gemm_tile_n(int cfg) { return cfg == 0 ? 64 : 32; }
+// Tile shapes (complex rows x complex columns).  With the 2 x 2 wave grid a shape needs rows
+// in multiples of 32 and columns in multiples of 16 (one f64 MFMA tile covers 16 rows and 8
+// complex columns).  Block dimensions are charge-sector sizes, so the planner picks, per
+// task, the shape with the least padded work.
+constexpr int CFG_M[GEMM_NCFG] = {64, 32, 128, 64, 96, 128, 32, 96, 96, 64};
+constexpr int CFG_N[GEMM_NCFG] = {64, 32, 32, 48, 48, 48, 48, 64, 32, 32};
+int gemm_tile_m(int cfg) { return CFG_M[cfg]; }
+int gemm_tile_n(int cfg) { return CFG_N[cfg]; }
 
 template <int BM, int BN>
 void launch_cfg(const GemmTask* tasks, const GemmSeg* segs, const int32_t* tile_task, int64_t total_tiles, int precision,
@@ -425,12 +424,20 @@ void launch_cfg(const GemmTask* tasks, const GemmSeg* segs, const int32_t* tile_
 void launch_gemm(const GemmTask* tasks, const GemmSeg* segs, const int32_t* tile_task, int64_t total_tiles, int cfg,
                  int precision, void* stream) {
   if (total_tiles <= 0) return;
-  if (cfg == 0)
-    launch_cfg<64, 64>(tasks, segs, tile_task, total_tiles, precision, (hipStream_t)stream);
-  else if (cfg == 1)
-    launch_cfg<32, 32>(tasks, segs, tile_task, total_tiles, precision, (hipStream_t)stream);
-  else
-    launch_cfg<128, 32>(tasks, segs, tile_task, total_tiles, precision, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  switch (cfg) {
+    case 0: launch_cfg<64, 64>(tasks, segs, tile_task, total_tiles, precision, s); break;
+    case 1: launch_cfg<32, 32>(tasks, segs, tile_task, total_tiles, precision, s); break;
+    case 2: launch_cfg<128, 32>(tasks, segs, tile_task, total_tiles, precision, s); break;
+    case 3: launch_cfg<64, 48>(tasks, segs, tile_task, total_tiles, precision, s); break;
+    case 4: launch_cfg<96, 48>(tasks, segs, tile_task, total_tiles, precision, s); break;
+    case 5: launch_cfg<128, 48>(tasks, segs, tile_task, total_tiles, precision, s); break;
+    case 6: launch_cfg<32, 48>(tasks, segs, tile_task, total_tiles, precision, s); break;
+    case 7: launch_cfg<96, 64>(tasks, segs, tile_task, total_tiles, precision, s); break;
+    case 8: launch_cfg<96, 32>(tasks, segs, tile_task, total_tiles, precision, s); break;
+    case 9: launch_cfg<64, 32>(tasks, segs, tile_task, total_tiles, precision, s); break;
+    default: throw Error(TDMPS_ERR_ARG, "bad GEMM tile configuration");
+  }
   check(hipGetLastError(), "gemm launch");
 }
 

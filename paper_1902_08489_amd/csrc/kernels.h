@@ -103,6 +103,7 @@ float dev_event_elapsed_ms(void* a, void* b);  // synchronises on b
 void launch_gemm(const GemmTask* tasks, const GemmSeg* segs, const int32_t* tile_task, int64_t total_tiles, int cfg,
                  int precision, void* stream);
 void launch_reduce(const ReduceTask* tasks, int ntasks, void* stream);
+constexpr int GEMM_NCFG = 10;  // tile shape configurations of launch_gemm
 int gemm_tile_m(int cfg);
 int gemm_tile_n(int cfg);
 void launch_copy(const CopyTask* tasks, int ntasks, void* stream);

@@ -33,6 +33,8 @@ struct SvdBatch {
   std::vector<SvdJob> jobs;
   DevBuf G, X, V, B, T;
   int64_t gsize = 0, bsize = 0, xsize = 0, vsize = 0, tsize = 0;
+  int sweeps = 0, rounds = 0;
+  double t_qr = 0;
 
   // row_side: the rows of M (left of the bond) become the canonical side, else its columns.
   void add(int R, int C, bool row_side) {
@@ -135,11 +137,14 @@ struct SvdBatch {
     }
     Staging st;
     const QrMat* dq = st.put(ctx, qm);
+    const double tq = wall_seconds();
     for (int j0 = 0; j0 < maxn; j0 += QR_PANEL) {
       launch_qr_panel(dq, nm, j0, ctx->stream);
       launch_qr_apply(dq, nm, cblocks, j0, 0, ctx->stream);
     }
     launch_qr_rt(dq, nm, ctx->stream);
+    dev_sync(ctx->stream);
+    t_qr = wall_seconds() - tq;
     const SvdMat* dm = st.put(ctx, xm);
     launch_svd_init(dm, nm, ctx->stream);
     DevBuf counter(sizeof(int32_t));
@@ -156,6 +161,8 @@ struct SvdBatch {
       converged = rot == 0;
     }
     TDMPS_REQUIRE(converged, TDMPS_ERR_NUMERIC, "Jacobi SVD did not converge");
+    sweeps = sweeps_done;
+    rounds = sweeps_done * maxrounds;
     if (std::getenv("TDMPS_SVD_STATS"))
       std::fprintf(stderr, "svd: %d matrices, max n %d, %d rounds per sweep, %d sweeps\n", nm, maxn, maxrounds,
                    sweeps_done);
@@ -270,6 +277,10 @@ TruncResult split_theta(Contractor& C, const cplx* theta, const TwoLayout& tl, M
     cp.run(C.ctx);
   }
   b.run(C.ctx);
+  C.n_svd += 1;
+  C.svd_sweeps += b.sweeps;
+  C.svd_rounds += b.rounds;
+  C.t_qr += b.t_qr;
   TruncResult res;
   auto kept = select(b, Dmax, cutoff, &res.discarded, &res.norm2);
   // new middle bond
@@ -360,6 +371,10 @@ void right_canonicalize(Contractor& C, Mps* m, double cutoff) {
       cp.run(C.ctx);
     }
     b.run(C.ctx);
+    C.n_svd += 1;
+    C.svd_sweeps += b.sweeps;
+    C.svd_rounds += b.rounds;
+    C.t_qr += b.t_qr;
     double disc, n2;
     auto kept = select(b, 1 << 30, cutoff, &disc, &n2);
     Bond nb;

@@ -234,7 +234,23 @@ void GemmPlan::finalize(Ctx* ctx) {
   }
   // tile shape per task: 64x64 for wide outputs, 128x32 for tall narrow ones (the
   // channel-stacked L*theta products), 32x32 otherwise
-  auto pick = [](const GemmTask& t) { return t.n > 40 && t.m > 40 ? 0 : (t.m >= 96 ? 2 : 1); };
+  // Tile shape per task: least padded MFMA work divided by the shape's relative throughput
+  // (measured on aligned shapes with enough tiles to fill the chip, FP64).
+  static const double eff[GEMM_NCFG] = {1.0, 0.92, 0.9, 0.96, 0.82, 0.8, 0.94, 0.85, 0.8, 0.97};
+  auto pick = [](const GemmTask& t) {
+    int best = 0;
+    double bc = 1e300;
+    for (int c = 0; c < NCFG; ++c) {
+      const int bm = gemm_tile_m(c), bn = gemm_tile_n(c);
+      const double tiles = (double)((t.m + bm - 1) / bm) * ((t.n + bn - 1) / bn);
+      const double cost = tiles * bm * bn / eff[c];
+      if (cost < bc) {
+        bc = cost;
+        best = c;
+      }
+    }
+    return best;
+  };
   for (int cfg = 0; cfg < NCFG; ++cfg) {
     std::vector<GemmTask> sel;
     int64_t base = 0;

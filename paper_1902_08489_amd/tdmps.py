@@ -132,7 +132,7 @@ class Context:
         self.h = h
 
     def counters(self):
-        out = np.zeros(8)
+        out = np.zeros(16)
         _check(_LIB.tdmps_ctx_counters(self.h, _dp(out)))
         return out
 
