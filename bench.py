@@ -158,7 +158,8 @@ def main():
         krylov = {"steps_per_s": args.krylov / dt, "s_per_step": dt / args.krylov, "m": args.krylov_m,
                   "sweeps_per_fit": 1,
                   "phase_seconds_last_step": {"heff": cnt[2], "env": cnt[3], "svd": cnt[4], "svd_qr": cnt[15],
-                                              "premix": cnt[5], "sandwich_total": cnt[6]},
+                                              "premix": cnt[5], "sandwich_total": cnt[6],
+                                              "host_planning_in_heff_env": cnt[16]},
                   "counts_last_step": {"heff": int(cnt[12]), "env_updates": int(cnt[13]), "svd": int(cnt[11]),
                                        "sandwiches": int(cnt[14]), "jacobi_sweeps": int(cnt[9]),
                                        "jacobi_rounds": int(cnt[10])},

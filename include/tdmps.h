@@ -100,11 +100,13 @@ tdmps_status tdmps_ctx_destroy(tdmps_ctx ctx);
  * out[7] = executed environment-update flops, out[8] = executed premix flops, out[9] / out[10]
  * = Jacobi sweeps / rounds summed over the SVDs, out[11..14] = number of SVD truncations,
  * H_eff applications, environment updates and sandwiches, out[15] = seconds in the QR
- * preconditioning.  After tdmps_heff_apply planning, out[0..7] describe the plan instead:
+ * preconditioning, out[16] = host seconds spent building GEMM plans (included in the H_eff
+ * and environment times), out[17..19] = 0.  After tdmps_heff_apply planning, out[0..7]
+ * describe the plan instead:
  * algorithmic flops, executed flops of the two stages, bytes of the intermediate, task and
  * segment counts of the two stages. */
-#define TDMPS_NCOUNTERS 16
-tdmps_status tdmps_ctx_counters(tdmps_ctx ctx, double* out16);
+#define TDMPS_NCOUNTERS 20
+tdmps_status tdmps_ctx_counters(tdmps_ctx ctx, double* out);
 tdmps_status tdmps_ctx_reset_counters(tdmps_ctx ctx);
 
 /* ---------------------------------------------------------------- Hamiltonian MPO

@@ -52,6 +52,7 @@ void publish(Ctx* ctx, const Contractor& C) {
   ctx->counters[13] = C.n_env;
   ctx->counters[14] = C.n_sandwich;
   ctx->counters[15] = C.t_qr;
+  ctx->counters[16] = C.t_plan;
 }
 
 void check_prm(const tdmps_fit_params* p) {
@@ -103,10 +104,10 @@ extern "C" tdmps_status tdmps_ctx_destroy(tdmps_ctx ctx) {
   });
 }
 
-extern "C" tdmps_status tdmps_ctx_counters(tdmps_ctx ctx, double* out16) {
+extern "C" tdmps_status tdmps_ctx_counters(tdmps_ctx ctx, double* out) {
   return guard([&] {
-    TDMPS_REQUIRE(ctx && out16, TDMPS_ERR_ARG, "NULL argument");
-    for (int i = 0; i < TDMPS_NCOUNTERS; ++i) out16[i] = ctx->counters[i];
+    TDMPS_REQUIRE(ctx && out, TDMPS_ERR_ARG, "NULL argument");
+    for (int i = 0; i < TDMPS_NCOUNTERS; ++i) out[i] = ctx->counters[i];
   });
 }
 

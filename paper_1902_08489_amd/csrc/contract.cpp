@@ -280,7 +280,9 @@ Env env_left_update(Contractor& C, const SideOps& ops, const Mps*, const cplx* b
     }
     tnonzero[t] = started;
   }
+  const double tb1 = wall_seconds();
   p1.run(C.ctx, C.precision);
+  const double te1 = wall_seconds();
   // L'_v[t, t'] = sum_{s, sig} conj(C[s, sig, t])^T T_v[s, sig, t']
   GemmPlan p2;
   for (int r = 0; r < (int)runs.size(); ++r) {
@@ -310,7 +312,9 @@ Env env_left_update(Contractor& C, const SideOps& ops, const Mps*, const cplx* b
         }
     }
   }
+  const double tb2 = wall_seconds();
   p2.run(C.ctx, C.precision);
+  C.t_plan += (tb1 - t0) + (tb2 - te1) + p1.host_s + p2.host_s;
   C.env_flops += p1.flops + p2.flops;
   C.t_env += wall_seconds() - t0;
   C.n_env += 1;
@@ -380,7 +384,9 @@ Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, co
     }
     tnonzero[t] = started;
   }
+  const double tb1 = wall_seconds();
   p1.run(C.ctx, C.precision);
+  const double te1 = wall_seconds();
   // R'_v[s, s'] = sum_{sig, t} conj(C[s, sig, t]) T_v[s', sig, t]^T
   GemmPlan p2;
   for (int r = 0; r < (int)runs.size(); ++r) {
@@ -408,7 +414,9 @@ Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, co
       }
     }
   }
+  const double tb2 = wall_seconds();
   p2.run(C.ctx, C.precision);
+  C.t_plan += (tb1 - t0) + (tb2 - te1) + p1.host_s + p2.host_s;
   C.env_flops += p1.flops + p2.flops;
   C.t_env += wall_seconds() - t0;
   C.n_env += 1;
@@ -426,6 +434,7 @@ void heff_apply(Contractor& C, const SideOps& lops, const SideOps& rops, const c
                 const Bond& bra_r, cplx alpha, bool accumulate, double* alg_flops) {
   const double t0 = wall_seconds();
   auto plan = heff_plan(C, lops, rops, theta_in, kl, ket_l, ket_r, theta_out, bl, bra_l, bra_r, alpha, accumulate);
+  C.t_plan += wall_seconds() - t0;
   plan->launch(C.ctx, C.precision);
   dev_sync(C.ctx->stream);
   C.heff_flops += plan->p1.flops + plan->p2.flops;
@@ -456,23 +465,31 @@ std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const Si
       v = e;
     }
   }
-  // final stage segments per output block, collecting the T blocks they need
-  struct TKey {
-    int r, s, s1, s2p, tk;
+  // T is stored per row block (run r, bra sector s, s1): rows (channel of the run, a), columns
+  // (s2', b') for the s2' needed by the final stage.  By charge conservation the ket sector of
+  // b' depends only on (s, s1, s2') and the run's channel charge, so every left pattern
+  // (s1, s1') of the run contributes to the whole row block with one product against the
+  // contiguous theta columns (s1', s2' = lo..hi) of its ket sector.
+  const int nbs = bra_l.nsec();
+  struct Row {
+    int r, s, s1, mask = 0;
+    int tk[4] = {-1, -1, -1, -1};
+    int lo = 4, hi = -1, width = 0;
+    int coff[4] = {0, 0, 0, 0};
+    int64_t off = -1;
   };
-  std::map<std::tuple<int, int, int, int, int>, int> tindex;
-  std::vector<TKey> tkeys;
+  std::vector<int> row_of(runs.size() * (size_t)nbs * 4, -1);
+  std::vector<Row> rows;
   struct FSeg {
-    int tkey;
+    int row, s2p;
     const OpRef* ref;
-    int tb;
   };
   std::vector<std::vector<FSeg>> fsegs;  // per output block
   struct OBlk {
     int s, sig, tb;
   };
   std::vector<OBlk> oblk;
-  for (int s = 0; s < bra_l.nsec(); ++s)
+  for (int s = 0; s < nbs; ++s)
     for (int sig = 0; sig < 16; ++sig) {
       int tb = bl.rs[s][sig];
       if (tb < 0) continue;
@@ -489,80 +506,100 @@ std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const Si
         const OpRef& ref = ro.ref[k];
         int tk = ref.src->grp[ref.grp].ket_of[tb];
         if (tk < 0) continue;
-        auto key = std::make_tuple(r, s, s1, s2p, tk);
-        auto it = tindex.find(key);
-        int id;
-        if (it == tindex.end()) {
-          id = (int)tkeys.size();
-          tindex[key] = id;
-          tkeys.push_back({r, s, s1, s2p, tk});
-        } else {
-          id = it->second;
+        int& id = row_of[((size_t)r * nbs + s) * 4 + s1];
+        if (id < 0) {
+          id = (int)rows.size();
+          Row nr;
+          nr.r = r;
+          nr.s = s;
+          nr.s1 = s1;
+          rows.push_back(nr);
         }
-        fsegs[ob].push_back({id, &ref, tb});
+        Row& row = rows[id];
+        TDMPS_REQUIRE(row.tk[s2p] < 0 || row.tk[s2p] == tk, TDMPS_ERR_NUMERIC, "internal: T column sector");
+        row.tk[s2p] = tk;
+        row.mask |= 1 << s2p;
+        fsegs[ob].push_back({id, s2p, &ref});
       }
     }
   }
   // T stage
-  std::vector<int64_t> toff(tkeys.size(), -1);
   int64_t tsize = 0;
   GemmPlan& p1 = plan->p1;
-  for (size_t t = 0; t < tkeys.size(); ++t) {
-    const TKey& K = tkeys[t];
-    const Run& run = runs[K.r];
+  std::vector<size_t> row_task(rows.size(), (size_t)-1);
+  for (size_t ri = 0; ri < rows.size(); ++ri) {
+    Row& R = rows[ri];
+    const Run& run = runs[R.r];
     const ChanOps& lo = lops.ch[run.v0];
-    int Ds = bra_l.dim[K.s], Dtk = ket_r.dim[K.tk];
+    const int Ds = bra_l.dim[R.s];
     bool started = false;
     for (size_t k = 0; k < lo.pat.size(); ++k) {
-      if ((lo.pat[k] >> 2) != K.s1) continue;
-      int s1p = lo.pat[k] & 3;
+      if ((lo.pat[k] >> 2) != R.s1) continue;
+      const int s1p = lo.pat[k] & 3;
       const OpRef& ref = lo.ref[k];
-      int sk = ref.src->grp[ref.grp].ket_of[K.s];
+      const int sk = ref.src->grp[ref.grp].ket_of[R.s];
       if (sk < 0) continue;
-      int sig_in = s1p * 4 + K.s2p;
-      if (kl.rs[sk][sig_in] != K.tk) continue;
-      int Dsk = ket_l.dim[sk];
       if (!started) {
-        toff[t] = tsize;
-        tsize += (int64_t)run.n * Ds * Dtk;
-        p1.begin_task(nullptr, 0, Dtk, run.n * Ds, Dtk, 1, false);
+        // columns: every s2' between the lowest and highest needed one whose ket sector exists
+        for (int q = 0; q < 4; ++q)
+          if (R.mask >> q & 1) {
+            R.lo = std::min(R.lo, q);
+            R.hi = std::max(R.hi, q);
+          }
+        for (int q = R.lo; q <= R.hi; ++q) {
+          const int tk = kl.rs[sk][s1p * 4 + q];
+          TDMPS_REQUIRE(R.tk[q] < 0 || R.tk[q] == tk, TDMPS_ERR_NUMERIC, "internal: theta column sector");
+          R.tk[q] = tk;
+          R.coff[q] = R.width;
+          if (tk >= 0) R.width += ket_r.dim[tk];
+        }
+        if (R.width == 0) break;
+        R.off = tsize;
+        tsize += (int64_t)run.n * Ds * R.width;
+        row_task[ri] = p1.tasks.size();
+        p1.begin_task(nullptr, 0, R.width, run.n * Ds, R.width, 1, false);
         started = true;
       }
+      int first = -1;
+      for (int q = R.lo; q <= R.hi; ++q) {
+        const int tk = kl.rs[sk][s1p * 4 + q];
+        TDMPS_REQUIRE(tk == R.tk[q], TDMPS_ERR_NUMERIC, "internal: theta column sector");
+        if (tk >= 0 && first < 0) first = q;
+      }
+      const int Dsk = ket_l.dim[sk];
       const cplx* A = ref.src->stack(ref.grp, sk) + (int64_t)ref.idx * Ds * Dsk;
-      const cplx* B = theta_in + kl.panel_off[sk] + kl.col[sk][sig_in];
+      const cplx* B = theta_in + kl.panel_off[sk] + kl.col[sk][s1p * 4 + first];
       p1.add_seg(A, 0, 0, Dsk, OP_N, B, 0, 0, kl.width[sk], OP_N, Dsk, 1, cplx{ref.coef, 0.0});
     }
   }
   plan->T = DevBuf(tsize * sizeof(cplx));
   cplx* Tb = plan->T.c();
-  {
-    size_t ti = 0;
-    for (size_t t = 0; t < tkeys.size(); ++t)
-      if (toff[t] >= 0) p1.tasks[ti++].C = Tb + toff[t];
-  }
+  for (size_t ri = 0; ri < rows.size(); ++ri)
+    if (row_task[ri] != (size_t)-1) p1.tasks[row_task[ri]].C = Tb + rows[ri].off;
   // final stage
   GemmPlan& p2 = plan->p2;
-  double alg = 0;
   for (size_t ob = 0; ob < oblk.size(); ++ob) {
     int s = oblk[ob].s, sig = oblk[ob].sig, tb = oblk[ob].tb;
     int Ds = bra_l.dim[s], Dt = bra_r.dim[tb];
     bool started = false;
     for (auto& fs : fsegs[ob]) {
-      if (toff[fs.tkey] < 0) continue;
-      const TKey& K = tkeys[fs.tkey];
-      const Run& run = runs[K.r];
-      int Dtk = ket_r.dim[K.tk];
+      const Row& R = rows[fs.row];
+      if (R.off < 0) continue;
+      const Run& run = runs[R.r];
+      const int tk = R.tk[fs.s2p];
+      const int Dtk = ket_r.dim[tk];
       if (!started) {
         p2.begin_task(theta_out + bl.panel_off[s] + bl.col[s][sig], 0, bl.width[s], Ds, Dt, 1, true);
         started = true;
       }
       const OpRef& ref = *fs.ref;
-      const cplx* A = Tb + toff[fs.tkey];
-      const cplx* B = ref.src->stack(ref.grp, K.tk) + (int64_t)ref.idx * Dt * Dtk;
-      p2.add_seg(A, 0, (int64_t)Ds * Dtk, Dtk, OP_N, B, 0, (int64_t)Dt * Dtk, Dtk, OP_T, Dtk, run.n,
+      const cplx* A = Tb + R.off + R.coff[fs.s2p];
+      const cplx* B = ref.src->stack(ref.grp, tk) + (int64_t)ref.idx * Dt * Dtk;
+      p2.add_seg(A, 0, (int64_t)Ds * R.width, R.width, OP_N, B, 0, (int64_t)Dt * Dtk, Dtk, OP_T, Dtk, run.n,
                  cmul(cplx{ref.coef, 0.0}, alpha));
     }
   }
+  double alg = 0;
   // algorithmic count in the plain order (L theta) -> W -> (. R): every channel of the outer
   // cuts against every compatible block.
   {

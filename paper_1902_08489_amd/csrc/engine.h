@@ -180,6 +180,7 @@ struct GemmPlan {
   std::vector<GemmTask> tasks;
   std::vector<GemmSeg> segs;
   double flops = 0;  // executed flops (8 per complex multiply-add)
+  double host_s = 0;  // host seconds spent in finalize() by run()
   int begin_task(cplx* C, int64_t bsC, int ldc, int m, int n, int nbatch, bool accum);
   void add_seg(const cplx* A, int64_t bsA, int64_t rsA, int lda, int opA, const cplx* B, int64_t bsB, int64_t rsB,
                int ldb, int opB, int k, int nred, cplx alpha);
@@ -227,6 +228,7 @@ struct Contractor {
   // wall-clock seconds per phase (every phase ends with a stream synchronisation)
   double t_heff = 0, t_env = 0, t_mix = 0, t_svd = 0, t_sandwich = 0, t_qr = 0;
   double svd_sweeps = 0, svd_rounds = 0, n_svd = 0, n_heff = 0, n_env = 0, n_sandwich = 0;
+  double t_plan = 0;  // host seconds building and finalising GEMM plans (H_eff and environments)
 };
 
 double wall_seconds();

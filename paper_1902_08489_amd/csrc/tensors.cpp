@@ -287,7 +287,9 @@ void GemmPlan::launch(Ctx* ctx, int precision) {
 }
 
 void GemmPlan::run(Ctx* ctx, int precision) {
+  const double t0 = wall_seconds();
   finalize(ctx);
+  host_s += wall_seconds() - t0;
   launch(ctx, precision);
   dev_sync(ctx->stream);
 }

@@ -48,6 +48,8 @@ _I32 = ct.POINTER(ct.c_int32)
 _I64 = ct.POINTER(ct.c_int64)
 _U8 = ct.POINTER(ct.c_uint8)
 
+NCOUNTERS = 20  # TDMPS_NCOUNTERS of include/tdmps.h
+
 _SIGS = {
     "tdmps_last_error": (ct.c_char_p, []),
     "tdmps_ctx_create": (ct.c_int32, [ct.c_int32, _P, _PP]),
@@ -132,7 +134,7 @@ class Context:
         self.h = h
 
     def counters(self):
-        out = np.zeros(16)
+        out = np.zeros(NCOUNTERS)
         _check(_LIB.tdmps_ctx_counters(self.h, _dp(out)))
         return out
 
