@@ -118,7 +118,7 @@ void launch_scale(cplx* x, int64_t n, cplx alpha, void* stream);
 // panel j0 to the trailing columns of G (mode 0) or Q's panel to B (mode 1) over total_blocks
 // = sum ceil(k / QR_PANEL) column blocks; X = R^H; finish: B = [V; 0], X <- X Sigma^{-1} with
 // sigma[j * max_n + c] the column norms of X.
-void launch_qr_panel(const QrMat* mats, int nmats, int j0, void* stream);
+void launch_qr_panel(const QrMat* mats, int nmats, int j0, int max_rows, void* stream);  // max_rows >= ell - j0
 void launch_qr_apply(const QrMat* mats, int nmats, int total_blocks, int j0, int mode, void* stream);
 void launch_qr_rt(const QrMat* mats, int nmats, void* stream);
 void launch_qr_finish(const QrMat* mats, int nmats, const double* sigma, int max_k, void* stream);

@@ -153,6 +153,151 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const QrMat* __restrict__
   for (int e = t; e < QB * QB; e += 256) T[e] = Ts[e / QB][e % QB];
 }
 
+// Register-resident variant of qr_panel_kernel for panels of at most 256 * RPT rows (RPT <= 4;
+// taller panels would spill and use qr_panel_kernel): thread t
+// holds rows j0 + t + 256 i (i < RPT) of the 16 panel columns, so a reflector step costs two
+// workgroup reductions and no memory traffic; the panel is read once and written once.
+template <int RPT>
+__global__ __launch_bounds__(256) void qr_panel_reg_kernel(const QrMat* __restrict__ mats, int j0) {
+  const QrMat m = mats[blockIdx.x];
+  if (j0 >= m.nsv) return;  // uniform
+  const int nb = min(QB, m.nsv - j0);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  double2* G = (double2*)m.G;
+  const int64_t ld = m.ell;
+  __shared__ double part[4][2 * QB];
+  __shared__ double2 red[QB];
+  __shared__ double2 Ts[QB][QB];
+  __shared__ double2 bc;
+  double2 x[RPT][QB];
+#pragma clang loop unroll(full)
+  for (int i = 0; i < RPT; ++i) {
+    const int row = j0 + t + 256 * i;
+#pragma clang loop unroll(full)
+    for (int c = 0; c < QB; ++c)
+      x[i][c] = (row < m.ell && c < nb) ? G[(j0 + c) * ld + row] : make_double2(0.0, 0.0);
+  }
+  for (int e = t; e < QB * QB; e += 256) Ts[e / QB][e % QB] = make_double2(0.0, 0.0);
+#pragma clang loop unroll(full)
+  for (int j = 0; j < QB; ++j) {
+    if (j < nb) {
+      const int col = j0 + j;
+      // |x[col+1 ..]|^2 and the diagonal element
+      double s = 0;
+#pragma clang loop unroll(full)
+      for (int i = 0; i < RPT; ++i) {
+        const int row = j0 + t + 256 * i;
+        if (row > col && row < m.ell) s += x[i][j].x * x[i][j].x + x[i][j].y * x[i][j].y;
+      }
+      s = wsum(s);
+      __syncthreads();  // previous users of part[], bc and red[] are done
+      if (lane == 0) part[wave][0] = s;
+#pragma clang loop unroll(full)
+      for (int i = 0; i < RPT; ++i)
+        if (j0 + t + 256 * i == col) bc = x[i][j];
+      __syncthreads();
+      const double xs = (part[0][0] + part[1][0]) + (part[2][0] + part[3][0]);
+      const double2 alpha = bc;
+      const double aa = sqrt(alpha.x * alpha.x + alpha.y * alpha.y);
+      double tau = 0;
+      if (xs > 0) {
+        const double nrm = sqrt(aa * aa + xs);
+        const double2 ph = aa > 0 ? make_double2(alpha.x / aa, alpha.y / aa) : make_double2(1.0, 0.0);
+        const double v0m = aa + nrm;
+        const double2 inv0 = make_double2(ph.x / v0m, -ph.y / v0m);
+        tau = 2.0 / (1.0 + xs / (v0m * v0m));
+#pragma clang loop unroll(full)
+        for (int i = 0; i < RPT; ++i) {
+          const int row = j0 + t + 256 * i;
+          const double2 v = x[i][j];
+          if (row == col)
+            x[i][j] = make_double2(-ph.x * nrm, -ph.y * nrm);
+          else if (row > col)
+            x[i][j] = make_double2(v.x * inv0.x - v.y * inv0.y, v.x * inv0.y + v.y * inv0.x);
+        }
+      }
+      const int nd = nb - 1;
+      if (nd > 0) {
+        double acc[2 * (QB - 1)];
+#pragma clang loop unroll(full)
+        for (int q = 0; q < 2 * (QB - 1); ++q) acc[q] = 0;
+        if (tau != 0) {
+#pragma clang loop unroll(full)
+          for (int i = 0; i < RPT; ++i) {
+            const int row = j0 + t + 256 * i;
+            if (row >= col && row < m.ell) {
+              const double2 v = row == col ? make_double2(1.0, 0.0) : x[i][j];
+#pragma clang loop unroll(full)
+              for (int q = 0; q < QB - 1; ++q) {
+                if (q < nd) {
+                  // q < j: reflector q (row > j0 + q here); else panel column q + 1
+                  const double2 y = x[i][q < j ? q : q + 1];
+                  const double2 z = q < j ? cmulc(y, v) : cmulc(v, y);
+                  acc[2 * q] += z.x;
+                  acc[2 * q + 1] += z.y;
+                }
+              }
+            }
+          }
+        }
+#pragma clang loop unroll(full)
+        for (int q = 0; q < 2 * (QB - 1); ++q) {
+          if (q < 2 * nd) {
+            const double v = wsum(acc[q]);
+            if (lane == 0) part[wave][q] = v;
+          }
+        }
+        __syncthreads();
+        if (t < nd)
+          red[t] = make_double2((part[0][2 * t] + part[1][2 * t]) + (part[2][2 * t] + part[3][2 * t]),
+                                (part[0][2 * t + 1] + part[1][2 * t + 1]) + (part[2][2 * t + 1] + part[3][2 * t + 1]));
+        __syncthreads();
+        if (tau != 0) {
+#pragma clang loop unroll(full)
+          for (int c = j + 1; c < QB; ++c) {
+            if (c < nb) {
+              const double2 d = red[c - 1];
+              const double2 f = make_double2(tau * d.x, tau * d.y);
+#pragma clang loop unroll(full)
+              for (int i = 0; i < RPT; ++i) {
+                const int row = j0 + t + 256 * i;
+                if (row >= col && row < m.ell) {
+                  const double2 v = row == col ? make_double2(1.0, 0.0) : x[i][j];
+                  x[i][c] = make_double2(x[i][c].x - (v.x * f.x - v.y * f.y), x[i][c].y - (v.x * f.y + v.y * f.x));
+                }
+              }
+            }
+          }
+        }
+      }
+      // T[0:j, j] = -tau_j T[0:j, 0:j] e, T[j][j] = tau_j
+      if (t == 0) {
+        for (int a = 0; a < j; ++a) {
+          double sr = 0, si = 0;
+          for (int b = a; b < j; ++b) {
+            const double2 tv = Ts[a][b], ev = red[b];
+            sr += tv.x * ev.x - tv.y * ev.y;
+            si += tv.x * ev.y + tv.y * ev.x;
+          }
+          Ts[a][j] = make_double2(-tau * sr, -tau * si);
+        }
+        Ts[j][j] = make_double2(tau, 0.0);
+      }
+    }
+  }
+#pragma clang loop unroll(full)
+  for (int i = 0; i < RPT; ++i) {
+    const int row = j0 + t + 256 * i;
+    if (row < m.ell)
+#pragma clang loop unroll(full)
+      for (int c = 0; c < QB; ++c)
+        if (c < nb) G[(j0 + c) * ld + row] = x[i][c];
+  }
+  __syncthreads();
+  double2* T = (double2*)m.T + (int64_t)(j0 / QB) * QB * QB;
+  for (int e = t; e < QB * QB; e += 256) T[e] = Ts[e / QB][e % QB];
+}
+
 // Apply the block reflector of panel j0 to 16-column blocks.  mode 0: trailing columns of G,
 // A <- (I - V T V^H)^H A for the columns j0 + nb .. k-1 right of the panel; mode 1:
 // A <- (I - V T V^H) A on the n columns of m.B (ell x n).  Only rows j0 .. ell-1 change.  Y = V^H A and the update A -= V Z (Z = T^H Y
@@ -307,9 +452,17 @@ __global__ __launch_bounds__(256) void qr_finish_kernel(const QrMat* __restrict_
 
 }  // namespace
 
-void launch_qr_panel(const QrMat* mats, int nmats, int j0, void* stream) {
+void launch_qr_panel(const QrMat* mats, int nmats, int j0, int max_rows, void* stream) {
   if (nmats <= 0) return;
-  hipLaunchKernelGGL(qr_panel_kernel, dim3(nmats), dim3(256), 0, (hipStream_t)stream, mats, j0);
+  hipStream_t s = (hipStream_t)stream;
+  if (max_rows <= 256)
+    hipLaunchKernelGGL(qr_panel_reg_kernel<1>, dim3(nmats), dim3(256), 0, s, mats, j0);
+  else if (max_rows <= 512)
+    hipLaunchKernelGGL(qr_panel_reg_kernel<2>, dim3(nmats), dim3(256), 0, s, mats, j0);
+  else if (max_rows <= 1024)
+    hipLaunchKernelGGL(qr_panel_reg_kernel<4>, dim3(nmats), dim3(256), 0, s, mats, j0);
+  else
+    hipLaunchKernelGGL(qr_panel_kernel, dim3(nmats), dim3(256), 0, s, mats, j0);
   check(hipGetLastError(), "qr panel launch");
 }
 

@@ -139,7 +139,10 @@ struct SvdBatch {
     const QrMat* dq = st.put(ctx, qm);
     const double tq = wall_seconds();
     for (int j0 = 0; j0 < maxn; j0 += QR_PANEL) {
-      launch_qr_panel(dq, nm, j0, ctx->stream);
+      int rows = 0;
+      for (int j = 0; j < nm; ++j)
+        if (j0 < jobs[j].n) rows = std::max(rows, jobs[j].ell - j0);
+      launch_qr_panel(dq, nm, j0, rows, ctx->stream);
       launch_qr_apply(dq, nm, cblocks, j0, 0, ctx->stream);
     }
     launch_qr_rt(dq, nm, ctx->stream);
