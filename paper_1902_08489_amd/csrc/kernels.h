@@ -108,8 +108,9 @@ int gemm_tile_m(int cfg);
 int gemm_tile_n(int cfg);
 void launch_copy(const CopyTask* tasks, int ntasks, void* stream);
 void launch_svd_init(const SvdMat* mats, int nmats, void* stream);  // V = identity
-// One round (block pairs of the circle schedule) for all matrices; total_pairs = sum nblk/2;
-// rot_counter is incremented once per block pair that rotated.
+// One round (block pairs of the circle schedule, round >= 0; or the diagonal round of a sweep,
+// round < 0) for all matrices; total_pairs = sum nblk/2; rot_counter is incremented once per
+// workgroup that rotated.  A sweep is the diagonal round followed by rounds 0 .. nblk-2.
 void launch_svd_round(const SvdMat* mats, int nmats, int64_t total_pairs, int round, double tol, int32_t* rot_counter,
                       void* stream);
 void launch_svd_norms(const SvdMat* mats, int nmats, int max_k, double* sigma_out, void* stream);

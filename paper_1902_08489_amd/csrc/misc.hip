@@ -134,13 +134,14 @@ __device__ __forceinline__ bool make_rot(double a, double b, double gr, double g
 }
 
 // One round of the block one-sided Jacobi method.  The columns of every matrix are cut into
-// blocks of SVD_BLOCK; workgroup i of the round owns block pair i of the circle schedule over
-// the blocks, i.e. 16 columns P.  It forms the Gram matrix M = P^H P on the FP64 MFMA units,
-// runs one cyclic Jacobi sweep on M in LDS (M <- J^H M J and Q <- Q J for every pair whose
-// overlap exceeds the tolerance, with the same test and rotation as the scalar method) and,
-// if any pair was rotated, overwrites P by P Q and the matching 16 columns of V by V Q, again
-// on the MFMA units.  M is formed afresh from the columns at every visit, so a sweep without
-// rotations certifies the pairwise test on the columns.
+// blocks of SVD_BLOCK; workgroup i of round r >= 0 owns block pair i of the circle schedule over
+// the blocks, workgroup i of the diagonal round (r < 0) the blocks 2i and 2i + 1, i.e. 16
+// columns P.  It forms the Gram matrix M = P^H P on the FP64 MFMA units, rotates the column
+// pairs of its round in LDS (M <- J^H M J and Q <- Q J for every pair whose overlap exceeds
+// the tolerance, with the same test and rotation as the scalar method) and, if any pair was
+// rotated, overwrites P by P Q and the matching 16 columns of V by V Q, again on the MFMA
+// units.  M is formed afresh from the columns at every visit, so a sweep without rotations
+// certifies the pairwise test on the columns.
 //
 // MFMA f64 16x16x4 lane layout: lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds
 // D[l/16 + 4e][l%16] in register e.  For the Gram matrix both operands are the element
@@ -171,9 +172,10 @@ __global__ __launch_bounds__(64 * SVD_WAVES) void svd_block_round_kernel(const S
   const int j = find_mat(mats, nmats, blockIdx.x);
   const SvdMat m = mats[j];
   const int i = (int)(blockIdx.x - m.pair_base);
+  const bool diag = round < 0;
   if (round >= m.nblk - 1 || i >= m.nblk / 2) return;  // uniform over the workgroup
-  int bI, bJ;
-  circle_pair(m.nblk, round, i, bI, bJ);
+  int bI = 2 * i, bJ = 2 * i + 1;
+  if (!diag) circle_pair(m.nblk, round, i, bI, bJ);
   if (t < SVD_PW) {
     const int c = (t < SVD_BLOCK ? bI : bJ) * SVD_BLOCK + (t % SVD_BLOCK);
     col[t] = c < m.k ? c : -1;
@@ -219,14 +221,27 @@ __global__ __launch_bounds__(64 * SVD_WAVES) void svd_block_round_kernel(const S
   }
   __syncthreads();
 
-  // one cyclic sweep on M by wave 0 (wave-synchronous LDS): lane l serves pair l / 8; the
-  // column step rotates rows l%8 and l%8 + 8 of M and Q, the row step columns l%8, l%8 + 8
+  // Rotations on M by wave 0 (wave-synchronous LDS): lane l serves pair l / 8; the column step
+  // rotates rows l%8 and l%8 + 8 of M and Q, the row step columns l%8, l%8 + 8.  A block-pair
+  // round rotates the 64 cross pairs (p in I, q in J) in 8 rounds of 8; the diagonal round of
+  // a sweep rotates the pairs inside I and inside J (7 rounds of 4 + 4).  Every column pair
+  // is thus rotated once per sweep (a cyclic Jacobi ordering).
   if (wave == 0) {
     const int pr = lane >> 3, sub = lane & 7;
     bool any = false;
-    for (int r = 0; r < SVD_PW - 1; ++r) {
+    const int nr = diag ? SVD_BLOCK - 1 : SVD_BLOCK;
+    for (int r = 0; r < nr; ++r) {
       int p, q;
-      circle_pair(SVD_PW, r, pr, p, q);
+      if (diag) {
+        circle_pair(SVD_BLOCK, r, pr & 3, p, q);
+        if (pr >= 4) {
+          p += SVD_BLOCK;
+          q += SVD_BLOCK;
+        }
+      } else {
+        p = pr;
+        q = SVD_BLOCK + ((pr + r) & (SVD_BLOCK - 1));
+      }
       Rot R;
       const double2 g = Ms[p][q];
       const bool rot = make_rot(Ms[p][p].x, Ms[q][q].x, g.x, g.y, tol, m.thr, R);

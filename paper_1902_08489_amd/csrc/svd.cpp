@@ -157,7 +157,7 @@ struct SvdBatch {
     int sweeps_done = 0;
     for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep, ++sweeps_done) {
       dev_zero(counter.p, sizeof(int32_t), ctx->stream);
-      for (int r = 0; r < maxrounds; ++r)
+      for (int r = -1; r < maxrounds; ++r)
         launch_svd_round(dm, nm, pairs, r, tol, (int32_t*)counter.p, ctx->stream);
       int32_t rot = 0;
       dev_d2h(&rot, counter.p, sizeof(int32_t), ctx->stream);
@@ -165,7 +165,7 @@ struct SvdBatch {
     }
     TDMPS_REQUIRE(converged, TDMPS_ERR_NUMERIC, "Jacobi SVD did not converge");
     sweeps = sweeps_done;
-    rounds = sweeps_done * maxrounds;
+    rounds = sweeps_done * (maxrounds + 1);
     if (std::getenv("TDMPS_SVD_STATS"))
       std::fprintf(stderr, "svd: %d matrices, max n %d, %d rounds per sweep, %d sweeps\n", nm, maxn, maxrounds,
                    sweeps_done);
