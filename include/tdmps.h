@@ -44,6 +44,7 @@ typedef struct tdmps_ctx_s* tdmps_ctx;
 typedef struct tdmps_mpo_s* tdmps_mpo;
 typedef struct tdmps_mps_s* tdmps_mps;
 typedef struct tdmps_heff_s* tdmps_heff;
+typedef struct tdmps_traj_s* tdmps_traj;
 typedef int32_t tdmps_status;
 
 enum {
@@ -199,6 +200,31 @@ tdmps_status tdmps_heff_apply(tdmps_heff op, const void* theta_in_dev, void* the
 /* Algorithmic flops of one apply (8 per complex multiply-add of the block products). */
 tdmps_status tdmps_heff_flops(tdmps_heff op, double* flops);
 tdmps_status tdmps_heff_destroy(tdmps_heff op);
+
+/* ---------------------------------------------------------------- differentiation
+ * Field-driven dynamics: H(t) = H0 + E(t) M with E(t) = amplitude * sin(omega t) *
+ * exp(-(t - t_center)^2 / (2 width^2)); the field enters through the one-body integrals of
+ * Eq. (hamil), h(t) = h0 + E(t) m.  tdmps_pulse_forward propagates psi0 by nsteps RK4 steps
+ * (Eqs. (k1-k4), (rk_add); stage times t, t+dt/2, t+dt/2, t+dt) and returns
+ * D = <psi_N|mu|psi_N> / <psi_N|psi_N>, keeping psi every checkpoint_every steps in the
+ * trajectory handle.  tdmps_pulse_backward returns dD/d(amplitude) by the adjoint of the
+ * discrete RK4 map: the states between checkpoints are recomputed and the adjoint stages
+ * are propagated backwards with the same fit / H_eff / environment kernels (H Hermitian, so
+ * the adjoint of an H application is an H application with -i dt -> +i dt).  At full bond
+ * dimension the result is the exact derivative of the discrete map; with truncation it is
+ * the derivative with the truncations held fixed.
+ *   H0       : MPO of H0 (its one-body part is replaced by h0 + E(t) m at every stage time).
+ *   h0, m    : L*L row-major one-body integrals of H0 and of the field coupling.
+ *   mu       : observable MPO (e.g. tdmps_mpo_one_body of the dipole integrals).
+ *   The trajectory owns copies of all inputs; destroy it with tdmps_traj_destroy. */
+typedef struct {
+  double amplitude, omega, t_center, width;
+} tdmps_pulse;
+tdmps_status tdmps_pulse_forward(tdmps_mpo H0, const double* h0, const double* m, tdmps_mpo mu, tdmps_mps psi0,
+                                 const tdmps_pulse* pulse, double dt, int32_t nsteps, int32_t checkpoint_every,
+                                 const tdmps_fit_params* prm, tdmps_traj* out, double* value);
+tdmps_status tdmps_pulse_backward(tdmps_traj traj, double* dvalue_damplitude);
+tdmps_status tdmps_traj_destroy(tdmps_traj traj);
 
 #ifdef __cplusplus
 }

@@ -92,3 +92,71 @@ def rk4_norm_eigenstate(E, dt):
     z = -1j * E * dt
     R = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
     return abs(R) ** 2
+
+
+# ---------------------------------------------------------------- field-driven dynamics
+# H(t) = H0 + E(t) M with E(t) = A f(t), f(t) = sin(omega t) exp(-(t - tc)^2 / (2 tau^2)): the
+# time-dependent Hamiltonian of the dipole coupling to a laser pulse (Methods: the one-body
+# integrals of Eq. (hamil) carry the field).  Observable: D = <psi_N|mu|psi_N> / <psi_N|psi_N>
+# after N RK4 steps of Eqs. (k1-k4, rk_add) with stage times t, t+dt/2, t+dt/2, t+dt.
+
+def pulse_shape(omega, tc, tau):
+    """f(t) such that E(t) = A f(t)."""
+    return lambda t: np.sin(omega * t) * np.exp(-((t - tc) ** 2) / (2 * tau ** 2))
+
+
+def rk4_field_forward(H0, M, psi0, f, A, dt, nsteps):
+    """All states psi_0 .. psi_N of the RK4 propagation under H0 + A f(t) M."""
+    Hmv = lambda t, v: H0 @ v + (A * f(t)) * (M @ v)
+    states = [np.asarray(psi0, dtype=np.complex128)]
+    for n in range(nsteps):
+        states.append(rk4(Hmv, states[-1], dt, t=n * dt))
+    return states
+
+
+def dipole_response(H0, M, mu, psi0, f, A, dt, nsteps):
+    """D(A) = <psi_N|mu|psi_N> / <psi_N|psi_N>."""
+    psi = rk4_field_forward(H0, M, psi0, f, A, dt, nsteps)[-1]
+    return float((psi.conj() @ (mu @ psi)).real / (psi.conj() @ psi).real)
+
+
+def dipole_response_gradient(H0, M, mu, psi0, f, A, dt, nsteps):
+    """dD/dA of the discrete RK4 map, by its adjoint (reverse mode through the stages).
+
+    Each step is linear, psi_{n+1} = P_n psi_n, so dD/dA = sum_n 2 Re <lam_{n+1}| dP_n/dA psi_n>
+    with lam_N = (mu - D) psi_N / |psi_N|^2 and lam_n = P_n^H lam_{n+1}.  With stage operators
+    A_s = -i dt H(t_s), k_s = A_s u_s (u_1 = psi, u_2 = psi + k1/2, u_3 = psi + k2/2,
+    u_4 = psi + k3) and psi' = psi + (k1 + 2 k2 + 2 k3 + k4)/6, the stage adjoints are
+    kb4 = lam/6, ub4 = A_4^H kb4, kb3 = lam/3 + ub4, ub3 = A_3^H kb3, kb2 = lam/3 + ub3/2,
+    ub2 = A_2^H kb2, kb1 = lam/6 + ub2/2, lam_n = lam + ub2 + ub3 + ub4 + A_1^H kb1, and the
+    step contributes sum_s 2 Re <kb_s| (-i dt f(t_s) M) u_s> = 2 dt sum_s f(t_s) Im <kb_s|M|u_s>.
+    Returns (D, dD/dA)."""
+    states = rk4_field_forward(H0, M, psi0, f, A, dt, nsteps)
+    H = lambda t: (lambda v: H0 @ v + (A * f(t)) * (M @ v))
+    psiN = states[-1]
+    nrm = (psiN.conj() @ psiN).real
+    D = (psiN.conj() @ (mu @ psiN)).real / nrm
+    lam = (mu @ psiN - D * psiN) / nrm
+    grad = 0.0
+    for n in range(nsteps - 1, -1, -1):
+        t = n * dt
+        psi = states[n]
+        ts = (t, t + dt / 2, t + dt / 2, t + dt)
+        k1 = -1j * dt * H(ts[0])(psi)
+        u2 = psi + k1 / 2
+        k2 = -1j * dt * H(ts[1])(u2)
+        u3 = psi + k2 / 2
+        k3 = -1j * dt * H(ts[2])(u3)
+        u4 = psi + k3
+        adj = lambda s, v: 1j * dt * H(ts[s])(v)  # A_s^H v (H Hermitian)
+        kb4 = lam / 6
+        ub4 = adj(3, kb4)
+        kb3 = lam / 3 + ub4
+        ub3 = adj(2, kb3)
+        kb2 = lam / 3 + ub3 / 2
+        ub2 = adj(1, kb2)
+        kb1 = lam / 6 + ub2 / 2
+        for s, (kb, u) in enumerate(((kb1, psi), (kb2, u2), (kb3, u3), (kb4, u4))):
+            grad += 2 * dt * f(ts[s]) * (kb.conj() @ (M @ u)).imag
+        lam = lam + ub2 + ub3 + ub4 + adj(0, kb1)
+    return float(D), float(grad)

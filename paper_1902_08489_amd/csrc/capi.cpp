@@ -5,6 +5,7 @@
 #include <memory>
 
 #include "drivers.h"
+#include "pulse.h"
 #include "engine.h"
 
 using namespace tdmps;
@@ -515,4 +516,67 @@ extern "C" tdmps_status tdmps_heff_flops(tdmps_heff h, double* flops) {
 
 extern "C" tdmps_status tdmps_heff_destroy(tdmps_heff h) {
   return guard([&] { delete h; });
+}
+
+// ---------------------------------------------------------------- differentiation
+struct tdmps_traj_s {
+  tdmps_ctx ctx = nullptr;
+  tdmps::PulseRun run;
+};
+
+extern "C" tdmps_status tdmps_pulse_forward(tdmps_mpo H0, const double* h0, const double* m, tdmps_mpo mu,
+                                            tdmps_mps psi0, const tdmps_pulse* pulse, double dt, int32_t nsteps,
+                                            int32_t checkpoint_every, const tdmps_fit_params* prm, tdmps_traj* out,
+                                            double* value) {
+  using namespace tdmps;
+  return guard([&] {
+    TDMPS_REQUIRE(H0 && h0 && m && mu && psi0 && pulse && out && value, TDMPS_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    check_prm(prm);
+    const int L = psi0->L;
+    TDMPS_REQUIRE(H0->host.L == L && mu->host.L == L, TDMPS_ERR_ARG, "length mismatch");
+    TDMPS_REQUIRE(nsteps >= 1 && checkpoint_every >= 1, TDMPS_ERR_ARG, "need nsteps >= 1 and checkpoint_every >= 1");
+    TDMPS_REQUIRE(std::isfinite(dt) && std::isfinite(pulse->amplitude) && std::isfinite(pulse->omega) &&
+                      std::isfinite(pulse->t_center) && std::isfinite(pulse->width) && pulse->width > 0,
+                  TDMPS_ERR_NUMERIC, "non-finite pulse parameters or width <= 0");
+    for (int i = 0; i < L * L; ++i)
+      TDMPS_REQUIRE(std::isfinite(h0[i]) && std::isfinite(m[i]), TDMPS_ERR_NUMERIC, "non-finite integrals");
+    std::unique_ptr<tdmps_traj_s> t(new tdmps_traj_s());
+    t->ctx = psi0->ctx;
+    PulseRun& r = t->run;
+    r.amplitude = pulse->amplitude;
+    r.omega = pulse->omega;
+    r.t_center = pulse->t_center;
+    r.width = pulse->width;
+    r.dt = dt;
+    r.nsteps = nsteps;
+    r.every = checkpoint_every;
+    r.prm = *prm;
+    r.h0.assign(h0, h0 + L * L);
+    r.m.assign(m, m + L * L);
+    r.Ht = H0->host;
+    r.Hm = H0->host;
+    r.Ht1 = H0->host;
+    r.M = build_mpo(L, m, nullptr, 0.0, false);
+    r.mu = mu->host;
+    Contractor C = make_contractor(psi0->ctx, prm);
+    pulse_forward(C, r, psi0);
+    publish(psi0->ctx, C);
+    *value = r.value;
+    *out = t.release();
+  });
+}
+
+extern "C" tdmps_status tdmps_pulse_backward(tdmps_traj traj, double* dvalue_damplitude) {
+  using namespace tdmps;
+  return guard([&] {
+    TDMPS_REQUIRE(traj && dvalue_damplitude, TDMPS_ERR_ARG, "NULL argument");
+    Contractor C = make_contractor(traj->ctx, &traj->run.prm);
+    *dvalue_damplitude = pulse_backward(C, traj->run);
+    publish(traj->ctx, C);
+  });
+}
+
+extern "C" tdmps_status tdmps_traj_destroy(tdmps_traj traj) {
+  return tdmps::guard([&] { delete traj; });
 }

@@ -37,6 +37,12 @@ class FitInfo(ct.Structure):
                 ("discarded_sum", ct.c_double), ("norm2", ct.c_double)]
 
 
+class Pulse(ct.Structure):
+    """E(t) = amplitude * sin(omega t) * exp(-(t - t_center)^2 / (2 width^2))."""
+    _fields_ = [("amplitude", ct.c_double), ("omega", ct.c_double), ("t_center", ct.c_double),
+                ("width", ct.c_double)]
+
+
 def fit_params(Dmax=64, n_sweeps=2, conv_tol=0.0, svd_cutoff=1e-12, precision=FP64, batched=1):
     return FitParams(Dmax, n_sweeps, conv_tol, svd_cutoff, precision, batched)
 
@@ -86,6 +92,10 @@ _SIGS = {
     "tdmps_heff_apply": (ct.c_int32, [_P, _P, _P]),
     "tdmps_heff_flops": (ct.c_int32, [_P, _D]),
     "tdmps_heff_destroy": (ct.c_int32, [_P]),
+    "tdmps_pulse_forward": (ct.c_int32, [_P, _D, _D, _P, _P, ct.POINTER(Pulse), ct.c_double, ct.c_int32, ct.c_int32,
+                                         ct.POINTER(FitParams), _PP, _D]),
+    "tdmps_pulse_backward": (ct.c_int32, [_P, _D]),
+    "tdmps_traj_destroy": (ct.c_int32, [_P]),
 }
 
 _LIB = None
@@ -383,3 +393,29 @@ class BlockLayout:
     def offset(self, b):
         row = self.blocks[b]
         return (int(row[6]) | (int(row[7]) << 31)) // 2
+
+
+class Trajectory:
+    """Field-driven RK4 run keeping checkpoints; .value = D, .backward() = dD/d(amplitude)."""
+
+    def __init__(self, H0, h0, m, mu, psi0, amplitude, omega, t_center, width, dt, nsteps, checkpoint_every=20,
+                 params=None):
+        params = params or fit_params()
+        h0 = np.ascontiguousarray(h0, dtype=np.float64)
+        m = np.ascontiguousarray(m, dtype=np.float64)
+        pulse = Pulse(float(amplitude), float(omega), float(t_center), float(width))
+        out, val = ct.c_void_p(), ct.c_double()
+        _check(_LIB.tdmps_pulse_forward(H0.h, _dp(h0), _dp(m), mu.h, psi0.h, ct.byref(pulse), float(dt), int(nsteps),
+                                        int(checkpoint_every), ct.byref(params), ct.byref(out), ct.byref(val)))
+        self.h = out
+        self.value = val.value
+
+    def backward(self):
+        g = ct.c_double()
+        _check(_LIB.tdmps_pulse_backward(self.h, ct.byref(g)))
+        return g.value
+
+    def __del__(self):
+        if getattr(self, "h", None) and _LIB is not None:
+            _LIB.tdmps_traj_destroy(self.h)
+            self.h = None

@@ -313,3 +313,27 @@ def test_slater_condon_at_large_L_single_double():
         i, a = rng.choice(occs), rng.choice([v for v in virt if (v & 1) == 0] if rng.random() < 0.5 else virt)
         m2 = m ^ (1 << int(i)) ^ (1 << int(a))
         assert abs(sc.element(m2, m) - sc.element(m, m2)) < 1e-12
+
+
+def test_dipole_gradient_matches_finite_differences():
+    """Adjoint gradient of the discrete RK4 map under a pulse (H(t) = H0 + A f(t) M) against
+    central differences of the forward map: O(h^2) agreement pins every stage adjoint."""
+    L = 4
+    h, eri, _ = synth.integrals(L)
+    occ = synth.ionized_determinant(L, 4)
+    space = fci.Space.sector(L, *synth.occ_charge(occ))
+    H0 = fci.hamiltonian(space, h, eri)
+    M = fci.one_body_operator(space, synth.dipole_matrix(L))
+    psi0 = space.restrict(mps.to_full(mps.from_occ(occ)))
+    f = propagate.pulse_shape(2.0, 0.3, 0.2)
+    A, dt, n = 0.7, 0.02, 30
+    D, g = propagate.dipole_response_gradient(H0, M, M, psi0, f, A, dt, n)
+    assert abs(D - propagate.dipole_response(H0, M, M, psi0, f, A, dt, n)) < 1e-13
+    hh = 1e-4
+    fd = (propagate.dipole_response(H0, M, M, psi0, f, A + hh, dt, n)
+          - propagate.dipole_response(H0, M, M, psi0, f, A - hh, dt, n)) / (2 * hh)
+    assert abs(g - fd) < 1e-8 * abs(fd)
+    # zero coupling: D does not depend on A
+    Z = 0 * M
+    _, g0 = propagate.dipole_response_gradient(H0, Z, M, psi0, f, A, dt, n)
+    assert abs(g0) < 1e-15
