@@ -69,6 +69,7 @@ def main():
     ap.add_argument("--krylov-m", type=int, default=12, help="Krylov dimension (12 in the benchmark definition)")
     ap.add_argument("--check", type=int, default=8, help="sampled outputs checked against Slater-Condon")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--per-block", type=int, default=1, help="also time one launch per block product (baseline)")
     ap.add_argument("--L", type=int, default=24)
     ap.add_argument("--D", type=int, default=1024)
     args = ap.parse_args()
@@ -117,6 +118,19 @@ def main():
     achieved = flops / (ms_kernel * 1e-3) / 1e12
 
     out = tout.cpu().numpy().view(np.complex128)
+    # batching baseline: the same H_eff*theta with one kernel launch per block product
+    batching = None
+    if args.per_block:
+        ctx.set_launch_mode(0)
+        op.apply(tin.data_ptr(), tout.data_ptr())
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        op.apply(tin.data_ptr(), tout.data_ptr())
+        torch.cuda.synchronize()
+        per_block_ms = (time.perf_counter() - tb) * 1e3
+        ctx.set_launch_mode(1)
+        batching = {"grouped_ms": ms_step, "per_block_ms": per_block_ms, "speedup": per_block_ms / ms_step,
+                    "launches_per_block_mode": int(plan_stats[4] + plan_stats[5])}
     check = None
     cpu = None
     if args.check > 0 or not args.no_cpu_baseline:
@@ -144,6 +158,7 @@ def main():
 
     krylov = None
     if args.krylov > 0:
+        os.environ["TDMPS_PROGRESS"] = "1"  # the library prints one line per Krylov vector
         bk, dk = synth.random_state(L, Nu, Nd, D, sigma=1.0, seed=L + 5)
         psi = T.MPS.from_blocks(ctx, bk, dk)
         prm = T.fit_params(Dmax=D, n_sweeps=1, precision=PREC[args.precision])
@@ -190,6 +205,7 @@ def main():
                                f"{ms_kernel:.2f} ms per step)"},
         "cpu_baseline": cpu,
         "krylov": krylov,
+        "batching": batching,
         "check": check,
         "plan": {"executed_flops_T_stage": plan_stats[1], "executed_flops_final_stage": plan_stats[2],
                  "T_bytes": plan_stats[3], "tasks": [int(plan_stats[4]), int(plan_stats[5])],

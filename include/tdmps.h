@@ -109,6 +109,11 @@ tdmps_status tdmps_ctx_destroy(tdmps_ctx ctx);
 #define TDMPS_NCOUNTERS 20
 tdmps_status tdmps_ctx_counters(tdmps_ctx ctx, double* out);
 tdmps_status tdmps_ctx_reset_counters(tdmps_ctx ctx);
+/* Launch mode of tdmps_heff_apply (Batching row of the benchmark set): 1 = every block product
+ * of a contraction stage in one grouped launch per tile shape (default); 0 = one kernel
+ * launch per block product, the per-block baseline.  Fits and time steps take the mode from
+ * tdmps_fit_params.batched instead. */
+tdmps_status tdmps_ctx_set_launch_mode(tdmps_ctx ctx, int32_t batched);
 
 /* ---------------------------------------------------------------- Hamiltonian MPO
  * Exact MPO of Eq. (hamil): H = sum_pq h_pq a+_{p s} a_{q s}

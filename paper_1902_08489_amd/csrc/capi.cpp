@@ -112,6 +112,14 @@ extern "C" tdmps_status tdmps_ctx_counters(tdmps_ctx ctx, double* out) {
   });
 }
 
+extern "C" tdmps_status tdmps_ctx_set_launch_mode(tdmps_ctx ctx, int32_t batched) {
+  return guard([&] {
+    TDMPS_REQUIRE(ctx, TDMPS_ERR_ARG, "NULL argument");
+    TDMPS_REQUIRE(batched == 0 || batched == 1, TDMPS_ERR_ARG, "launch mode must be 0 or 1");
+    ctx->batched = batched;
+  });
+}
+
 extern "C" tdmps_status tdmps_ctx_reset_counters(tdmps_ctx ctx) {
   return guard([&] {
     TDMPS_REQUIRE(ctx, TDMPS_ERR_ARG, "NULL argument");
@@ -491,7 +499,7 @@ extern "C" tdmps_status tdmps_heff_apply(tdmps_heff h, const void* in, void* out
       c->counters[6] = (double)h->plan->p1.segs.size();
       c->counters[7] = (double)h->plan->p2.segs.size();
     }
-    h->plan->launch(h->ctx, h->precision);
+    h->plan->launch(h->ctx, h->precision, h->ctx->batched != 0);
     dev_sync(h->ctx->stream);
   });
 }

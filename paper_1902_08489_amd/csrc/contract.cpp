@@ -41,7 +41,9 @@ struct MixRow {
   std::vector<std::pair<int, double>> src;  // (source channel, coefficient)
 };
 
-SideOps build_ops(Contractor& C, const Env& E, const MpoHost& W, int site, bool left) {
+// With ext != nullptr the premix products are appended to *ext (run by the caller) instead
+// of being run here.
+SideOps build_ops(Contractor& C, const Env& E, const MpoHost& W, int site, bool left, GemmPlan* ext = nullptr) {
   const double t0 = wall_seconds();
   struct Acc {
     Contractor& C;
@@ -129,9 +131,11 @@ SideOps build_ops(Contractor& C, const Env& E, const MpoHost& W, int site, bool 
     pend.push_back({g, cw, lo - sc.cls_start[cw], ncol, off});
     ++g;
   }
-  Staging st;
-  const cplx* dw = st.put(C.ctx, wmat);
-  GemmPlan plan;
+  ops.wmat.reset(new DevBuf(std::max<size_t>(wmat.size(), 1) * sizeof(cplx)));
+  dev_h2d(ops.wmat->p, wmat.data(), wmat.size() * sizeof(cplx), C.ctx->stream);
+  const cplx* dw = ops.wmat->c();
+  GemmPlan local;
+  GemmPlan& plan = ext ? *ext : local;
   const Blocks& eb = E.b;
   for (auto& p : pend) {
     const StackGroup& sg = ops.mix->grp[p.g];
@@ -145,8 +149,10 @@ SideOps build_ops(Contractor& C, const Env& E, const MpoHost& W, int site, bool 
       plan.add_seg(dw + p.off, 0, 0, p.ncol, OP_N, B + (int64_t)p.wlo * blk, 0, 0, (int)blk, OP_N, p.ncol, 1, ONE);
     }
   }
-  plan.run(C.ctx, TDMPS_FP64);
-  C.mix_flops += plan.flops;
+  if (!ext) {
+    plan.run(C.ctx, TDMPS_FP64, C.batched);
+    C.mix_flops += plan.flops;
+  }
   return ops;
 }
 
@@ -216,16 +222,16 @@ static std::vector<std::pair<Charge, int>> cut_groups(const MpoCut& c) {
   return g;
 }
 
-Env env_left_update(Contractor& C, const SideOps& ops, const Mps*, const cplx* bra_site, const SiteLayout& bl,
-                    const Bond& bra_l, const Bond& bra_r, const cplx* ket_site, const SiteLayout& kl,
-                    const Bond& ket_l, const Bond& ket_r, const MpoHost& W) {
-  const double t0 = wall_seconds();
+// Plans a left environment update: the T stage into p1, the contraction with the bra into p2
+// (run p1 before p2); T holds the intermediate and must outlive both runs.
+void env_left_plan(const SideOps& ops, const cplx* bra_site, const SiteLayout& bl, const Bond& bra_l,
+                   const Bond& bra_r, const cplx* ket_site, const SiteLayout& kl, const Bond& ket_l,
+                   const Bond& ket_r, const MpoHost& W, Ctx* ctx, GemmPlan& p1, GemmPlan& p2, DevBuf& T, Env& out) {
   const MpoCut& mc = W.cut[ops.cut];
-  Env out;
   out.cut = ops.cut;
   out.b.layout(bra_r, ket_r, cut_groups(mc));
   out.b.data = DevBuf(out.b.size * sizeof(cplx));
-  if (out.b.size) dev_zero(out.b.data.p, out.b.data.bytes, C.ctx->stream);
+  if (out.b.size) dev_zero(out.b.data.p, out.b.data.bytes, ctx->stream);
   auto runs = make_runs(mc, &ops, nullptr);
   // T_v[s, sig, t'] = sum_{sig'} Lop_v^{sig sig'}[s, s'] A_ket[s', sig', t']
   struct TKey {
@@ -252,8 +258,7 @@ Env env_left_update(Contractor& C, const SideOps& ops, const Mps*, const cplx* b
         }
     }
   }
-  DevBuf T(tsize * sizeof(cplx));
-  GemmPlan p1;
+  T = DevBuf(tsize * sizeof(cplx));
   std::vector<char> tnonzero(tkeys.size(), 0);
   for (size_t t = 0; t < tkeys.size(); ++t) {
     const TKey& K = tkeys[t];
@@ -280,11 +285,7 @@ Env env_left_update(Contractor& C, const SideOps& ops, const Mps*, const cplx* b
     }
     tnonzero[t] = started;
   }
-  const double tb1 = wall_seconds();
-  p1.run(C.ctx, C.precision);
-  const double te1 = wall_seconds();
   // L'_v[t, t'] = sum_{s, sig} conj(C[s, sig, t])^T T_v[s, sig, t']
-  GemmPlan p2;
   for (int r = 0; r < (int)runs.size(); ++r) {
     int v0 = runs[r].v0;
     int g = mc.cls_of[v0];
@@ -312,9 +313,20 @@ Env env_left_update(Contractor& C, const SideOps& ops, const Mps*, const cplx* b
         }
     }
   }
-  const double tb2 = wall_seconds();
-  p2.run(C.ctx, C.precision);
-  C.t_plan += (tb1 - t0) + (tb2 - te1) + p1.host_s + p2.host_s;
+}
+
+Env env_left_update(Contractor& C, const SideOps& ops, const Mps*, const cplx* bra_site, const SiteLayout& bl,
+                    const Bond& bra_l, const Bond& bra_r, const cplx* ket_site, const SiteLayout& kl,
+                    const Bond& ket_l, const Bond& ket_r, const MpoHost& W) {
+  const double t0 = wall_seconds();
+  GemmPlan p1, p2;
+  DevBuf T;
+  Env out;
+  env_left_plan(ops, bra_site, bl, bra_l, bra_r, ket_site, kl, ket_l, ket_r, W, C.ctx, p1, p2, T, out);
+  const double tb = wall_seconds();
+  p1.run(C.ctx, C.precision, C.batched);
+  p2.run(C.ctx, C.precision, C.batched);
+  C.t_plan += (tb - t0) + p1.host_s + p2.host_s;
   C.env_flops += p1.flops + p2.flops;
   C.t_env += wall_seconds() - t0;
   C.n_env += 1;
@@ -385,7 +397,7 @@ Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, co
     tnonzero[t] = started;
   }
   const double tb1 = wall_seconds();
-  p1.run(C.ctx, C.precision);
+  p1.run(C.ctx, C.precision, C.batched);
   const double te1 = wall_seconds();
   // R'_v[s, s'] = sum_{sig, t} conj(C[s, sig, t]) T_v[s', sig, t]^T
   GemmPlan p2;
@@ -415,7 +427,7 @@ Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, co
     }
   }
   const double tb2 = wall_seconds();
-  p2.run(C.ctx, C.precision);
+  p2.run(C.ctx, C.precision, C.batched);
   C.t_plan += (tb1 - t0) + (tb2 - te1) + p1.host_s + p2.host_s;
   C.env_flops += p1.flops + p2.flops;
   C.t_env += wall_seconds() - t0;
@@ -423,10 +435,10 @@ Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, co
   return out;
 }
 
-void HeffPlan::launch(Ctx* ctx, int precision) {
+void HeffPlan::launch(Ctx* ctx, int precision, bool batched) {
   if (!accumulate && out_size) dev_zero(out, out_size * sizeof(cplx), ctx->stream);
-  p1.launch(ctx, precision);
-  p2.launch(ctx, precision);
+  p1.launch(ctx, precision, batched);
+  p2.launch(ctx, precision, batched);
 }
 
 void heff_apply(Contractor& C, const SideOps& lops, const SideOps& rops, const cplx* theta_in, const TwoLayout& kl,
@@ -435,7 +447,7 @@ void heff_apply(Contractor& C, const SideOps& lops, const SideOps& rops, const c
   const double t0 = wall_seconds();
   auto plan = heff_plan(C, lops, rops, theta_in, kl, ket_l, ket_r, theta_out, bl, bra_l, bra_r, alpha, accumulate);
   C.t_plan += wall_seconds() - t0;
-  plan->launch(C.ctx, C.precision);
+  plan->launch(C.ctx, C.precision, C.batched);
   dev_sync(C.ctx->stream);
   C.heff_flops += plan->p1.flops + plan->p2.flops;
   if (alg_flops) *alg_flops = plan->alg_flops;
@@ -653,7 +665,7 @@ void form_theta(Contractor& C, const Mps* m, int i, cplx* theta, const TwoLayout
                   m->bond[i + 1].dim[mid], 1, ONE);
       }
     }
-  p.run(C.ctx, TDMPS_FP64);
+  p.run(C.ctx, TDMPS_FP64, C.batched);
 }
 
 cplx sandwich(Contractor& C, const MpoHost& O, const Mps* bra, const Mps* ket) {
@@ -681,6 +693,74 @@ cplx sandwich(Contractor& C, const MpoHost& O, const Mps* bra, const Mps* ket) {
 cplx overlap(Contractor& C, const Mps* a, const Mps* b) {
   MpoHost I = identity_mpo(a->L);
   return sandwich(C, I, a, b);
+}
+
+std::vector<cplx> sandwich_many(Contractor& C, const MpoHost& O, const std::vector<const Mps*>& bras,
+                                const Mps* ket) {
+  const double t0 = wall_seconds();
+  struct Acc {
+    Contractor& C;
+    double t0;
+    ~Acc() { C.t_sandwich += wall_seconds() - t0; }
+  } acc_{C, t0};
+  const size_t nb = bras.size();
+  C.n_sandwich += (double)nb;
+  std::vector<cplx> out(nb, cplx{0, 0});
+  if (nb == 0) return out;
+  for (const Mps* b : bras) {
+    TDMPS_REQUIRE(b->L == ket->L && b->L == O.L, TDMPS_ERR_ARG, "length mismatch");
+    TDMPS_REQUIRE(b->total == ket->total, TDMPS_ERR_SECTOR, "bra and ket have different total charge");
+  }
+  std::vector<Env> E;
+  E.reserve(nb);
+  for (const Mps* b : bras) E.push_back(env_left_boundary(C.ctx, b->bond[0], ket->bond[0]));
+  // Bras advance site by site together.  At each site the bras are taken in chunks: every
+  // chunk's premix products run as one grouped launch, then its two environment stages as one
+  // grouped launch each.  A chunk closes when its intermediates exceed the byte budget
+  // (TDMPS_SANDWICH_BUDGET_GB, default 1): small environments (chain ends, small D) share
+  // launches, large ones (D ~ 1000, several GB of intermediates each) go one bra at a time.
+  double budget_gb = 1;
+  if (const char* e = std::getenv("TDMPS_SANDWICH_BUDGET_GB")) budget_gb = std::atof(e);
+  const double budget = budget_gb * (double)(1ull << 30);
+  for (int i = 0; i < ket->L; ++i) {
+    std::vector<Env> N(nb);
+    size_t j0 = 0;
+    while (j0 < nb) {
+      const double tp = wall_seconds();
+      GemmPlan P0, P1, P2;
+      std::vector<SideOps> ops;
+      std::vector<DevBuf> T;
+      ops.reserve(nb - j0);
+      T.reserve(nb - j0);
+      double bytes = 0;
+      size_t j1 = j0;
+      while (j1 < nb && (j1 == j0 || bytes < budget)) {
+        const Mps* b = bras[j1];
+        ops.push_back(build_ops(C, E[j1], O, i, true, &P0));
+        T.emplace_back();
+        env_left_plan(ops.back(), b->site[i].c(), b->lay[i], b->bond[i], b->bond[i + 1], ket->site[i].c(),
+                      ket->lay[i], ket->bond[i], ket->bond[i + 1], O, C.ctx, P1, P2, T.back(), N[j1]);
+        bytes += (double)T.back().bytes + (ops.back().mix ? (double)ops.back().mix->data.bytes : 0.0);
+        ++j1;
+      }
+      const double tr = wall_seconds();
+      P0.run(C.ctx, TDMPS_FP64, C.batched);
+      C.mix_flops += P0.flops;
+      const double te = wall_seconds();
+      C.t_mix += te - tr;
+      P1.run(C.ctx, C.precision, C.batched);
+      P2.run(C.ctx, C.precision, C.batched);
+      C.t_plan += (tr - tp) + P0.host_s + P1.host_s + P2.host_s;
+      C.env_flops += P1.flops + P2.flops;
+      C.t_env += wall_seconds() - te;
+      C.n_env += (double)(j1 - j0);
+      j0 = j1;
+    }
+    E = std::move(N);
+  }
+  for (size_t j = 0; j < nb; ++j)
+    if (E[j].b.size) dev_d2h(&out[j], E[j].b.data.p, sizeof(cplx), C.ctx->stream);
+  return out;
 }
 
 }  // namespace tdmps

@@ -1,6 +1,8 @@
 // Time steps built from the fit: RK4 (Eqs. (k1-k4), (rk_add)) and Krylov (Eqs. (kry_non),
 // (kry_orth), (krylov_evo)).  The m x m Krylov algebra runs on the host in FP64.
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <complex>
 #include <memory>
 
@@ -166,6 +168,9 @@ Mps* krylov_step(Contractor& C, const MpoHost* H, const Mps* psi, double dt, int
                  const tdmps_fit_params& prm, std::vector<zd>* Nout, std::vector<zd>* Hout) {
   TDMPS_REQUIRE(m >= 2 && m <= 64, TDMPS_ERR_ARG, "Krylov dimension must be in [2, 64]");
   auto z = [](cplx c) { return zd(c.x, c.y); };
+  // optional progress lines on stderr (TDMPS_PROGRESS set): one per Krylov vector
+  const bool progress = std::getenv("TDMPS_PROGRESS") != nullptr;
+  const double t_start = wall_seconds();
   double n0 = overlap(C, psi, psi).x;
   TDMPS_REQUIRE(n0 > 0 && std::isfinite(n0), TDMPS_ERR_NUMERIC, "state has zero or non-finite norm");
   double s0 = std::sqrt(n0);
@@ -174,9 +179,17 @@ Mps* krylov_step(Contractor& C, const MpoHost* H, const Mps* psi, double dt, int
   scale_mps(C.ctx, phi[0].get(), cplx{1.0 / s0, 0.0});
   std::vector<zd> N((size_t)m * m, zd(0)), Hm((size_t)m * m, zd(0));
   N[0] = z(overlap(C, phi[0].get(), phi[0].get()));
+  MpoHost I = identity_mpo(psi->L);
+  auto bras = [&](int n) {
+    std::vector<const Mps*> b;
+    for (int j = 0; j < n; ++j) b.push_back(phi[j].get());
+    return b;
+  };
   for (int k = 0; k < m - 1; ++k) {
+    // H_jk = <phi_j|H|phi_k> for all j <= k in one batched sweep
+    const std::vector<cplx> hk = sandwich_many(C, *H, bras(k + 1), phi[k].get());
     for (int j = 0; j <= k; ++j) {
-      Hm[j * m + k] = z(sandwich(C, *H, phi[j].get(), phi[k].get()));
+      Hm[j * m + k] = z(hk[j]);
       Hm[k * m + j] = std::conj(Hm[j * m + k]);
     }
     std::vector<FitTerm> terms;
@@ -186,18 +199,24 @@ Mps* krylov_step(Contractor& C, const MpoHost* H, const Mps* psi, double dt, int
         terms.push_back({cplx{b.real(), b.imag()}, phi[j].get()});
       }
     std::unique_ptr<Mps> nxt(fit(C, H, cplx{1, 0}, phi[k].get(), terms, prm, nullptr));
+    if (progress)
+      std::fprintf(stderr, "krylov: vector %d of %d after %.1f s\n", k + 1, m - 1, wall_seconds() - t_start);
     double nn = overlap(C, nxt.get(), nxt.get()).x;
     TDMPS_REQUIRE(nn > 0 && std::isfinite(nn), TDMPS_ERR_SINGULAR, "Krylov vector vanished");
     scale_mps(C.ctx, nxt.get(), cplx{1.0 / std::sqrt(nn), 0.0});
     phi.push_back(std::move(nxt));
+    const std::vector<cplx> nk = sandwich_many(C, I, bras(k + 2), phi[k + 1].get());
     for (int j = 0; j <= k + 1; ++j) {
-      N[j * m + k + 1] = z(overlap(C, phi[j].get(), phi[k + 1].get()));
+      N[j * m + k + 1] = z(nk[j]);
       N[(k + 1) * m + j] = std::conj(N[j * m + k + 1]);
     }
   }
-  for (int j = 0; j < m; ++j) {
-    Hm[j * m + m - 1] = z(sandwich(C, *H, phi[j].get(), phi[m - 1].get()));
-    Hm[(m - 1) * m + j] = std::conj(Hm[j * m + m - 1]);
+  {
+    const std::vector<cplx> hl = sandwich_many(C, *H, bras(m), phi[m - 1].get());
+    for (int j = 0; j < m; ++j) {
+      Hm[j * m + m - 1] = z(hl[j]);
+      Hm[(m - 1) * m + j] = std::conj(Hm[j * m + m - 1]);
+    }
   }
   auto c = krylov_coefficients(m, N, Hm, dt, orthogonal);
   std::vector<FitTerm> terms;

@@ -105,6 +105,7 @@ struct tdmps_ctx_s {
   bool own_stream = false;
   void* ev[2] = {nullptr, nullptr};
   double counters[TDMPS_NCOUNTERS] = {0};
+  int batched = 1;  // launch mode of the H_eff handle API (tdmps_ctx_set_launch_mode)
   bool timing = false;
 };
 
@@ -173,6 +174,7 @@ struct SideOps {
   const Env* env = nullptr;
   std::vector<ChanOps> ch;
   std::unique_ptr<Blocks> mix;
+  std::unique_ptr<DevBuf> wmat;  // premix coefficients (device), alive until the premix plan ran
 };
 
 // ---------------------------------------------------------------- GEMM plans
@@ -187,14 +189,17 @@ struct GemmPlan {
   // device copies of the task lists (finalize) and asynchronous launch
   static constexpr int NCFG = GEMM_NCFG;
   DevBuf dsegs, dtasks[NCFG], dtile[NCFG], wspace, dred;
+  std::vector<int64_t> htile_base[NCFG];  // first tile of every task (per-task launches)
   std::vector<int64_t> red_base;
   int nred_tasks = 0;
   int ntask[NCFG] = {};
   int64_t ntiles[NCFG] = {};
   bool final_ = false;
   void finalize(Ctx* ctx);
-  void launch(Ctx* ctx, int precision);
-  void run(Ctx* ctx, int precision);  // finalize + launch + synchronise
+  // batched: one grouped launch per tile shape (default); else one launch per task (the
+  // per-block baseline the grouped launch is compared with)
+  void launch(Ctx* ctx, int precision, bool batched = true);
+  void run(Ctx* ctx, int precision, bool batched = true);  // finalize + launch + synchronise
   bool empty() const { return tasks.empty(); }
 };
 
@@ -259,7 +264,7 @@ struct HeffPlan {
   int64_t out_size = 0;
   bool accumulate = false;
   double alg_flops = 0;
-  void launch(Ctx* ctx, int precision);
+  void launch(Ctx* ctx, int precision, bool batched = true);
 };
 std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const SideOps& rops, const cplx* theta_in,
                                     const TwoLayout& kl, const Bond& ket_l, const Bond& ket_r, cplx* theta_out,
@@ -301,5 +306,8 @@ Mps* fit(Contractor& C, const MpoHost* H, cplx alpha, const Mps* psi, const std:
 
 void scale_mps(Ctx* ctx, Mps* m, cplx alpha);
 cplx overlap(Contractor& C, const Mps* a, const Mps* b);
+// <bra_j|O|ket> for all bras: the environment sweeps of all bras advance site by site together,
+// each premix / environment stage of all bras in one grouped launch.
+std::vector<cplx> sandwich_many(Contractor& C, const MpoHost& O, const std::vector<const Mps*>& bras, const Mps* ket);
 
 }  // namespace tdmps

@@ -182,7 +182,8 @@ __device__ __forceinline__ void split_bf16(double x, __bf16& h, __bf16& l) {
 template <int BM, int BN, int PREC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void gemm_kernel(const GemmTask* __restrict__ tasks,
                                                    const GemmSeg* __restrict__ segs,
-                                                   const int32_t* __restrict__ tile_task, int64_t total_tiles) {
+                                                   const int32_t* __restrict__ tile_task, int64_t total_tiles,
+                                                   int64_t tile_offset) {
   constexpr int BK = PREC == P64 ? 8 : 16;  // complex k per LDS stage (FP64: fewer live registers)
   constexpr int WM = BM / 2;                 // complex rows per wave
   constexpr int WN = BN / 2;                 // complex columns per wave
@@ -194,8 +195,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
   // One tile per workgroup.  Workgroup w runs on XCD w % 8; tiles are numbered so that
   // each XCD takes a contiguous range, keeping neighbouring tiles of a task in one L2.
   const int64_t per_xcd = (total_tiles + 7) / 8;
-  const int64_t tile = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (tile >= total_tiles) return;
+  const int64_t tile0 = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (tile0 >= total_tiles) return;
+  const int64_t tile = tile0 + tile_offset;
   const int ti = tile_task[tile];
   const GemmTask T = tasks[ti];
   const int64_t local = tile - T.tile_base;
@@ -409,33 +411,33 @@ int gemm_tile_n(int cfg) { return CFG_N[cfg]; }
 
 template <int BM, int BN>
 void launch_cfg(const GemmTask* tasks, const GemmSeg* segs, const int32_t* tile_task, int64_t total_tiles, int precision,
-                hipStream_t stream) {
+                hipStream_t stream, int64_t off) {
   const int64_t grid = 8 * ((total_tiles + 7) / 8);
   TDMPS_REQUIRE(grid < ((int64_t)1 << 31), TDMPS_ERR_ARG, "too many GEMM tiles in one launch");
   dim3 g((unsigned)grid), block(256);
   if (precision == TDMPS_FP32)
-    hipLaunchKernelGGL((gemm_kernel<BM, BN, P32>), g, block, 0, stream, tasks, segs, tile_task, total_tiles);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, P32>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
   else if (precision == TDMPS_BF16X3)
-    hipLaunchKernelGGL((gemm_kernel<BM, BN, PBF3>), g, block, 0, stream, tasks, segs, tile_task, total_tiles);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, PBF3>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
   else
-    hipLaunchKernelGGL((gemm_kernel<BM, BN, P64>), g, block, 0, stream, tasks, segs, tile_task, total_tiles);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, P64>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
 }
 
 void launch_gemm(const GemmTask* tasks, const GemmSeg* segs, const int32_t* tile_task, int64_t total_tiles, int cfg,
-                 int precision, void* stream) {
+                 int precision, void* stream, int64_t off) {
   if (total_tiles <= 0) return;
   hipStream_t s = (hipStream_t)stream;
   switch (cfg) {
-    case 0: launch_cfg<64, 64>(tasks, segs, tile_task, total_tiles, precision, s); break;
-    case 1: launch_cfg<32, 32>(tasks, segs, tile_task, total_tiles, precision, s); break;
-    case 2: launch_cfg<128, 32>(tasks, segs, tile_task, total_tiles, precision, s); break;
-    case 3: launch_cfg<64, 48>(tasks, segs, tile_task, total_tiles, precision, s); break;
-    case 4: launch_cfg<96, 48>(tasks, segs, tile_task, total_tiles, precision, s); break;
-    case 5: launch_cfg<128, 48>(tasks, segs, tile_task, total_tiles, precision, s); break;
-    case 6: launch_cfg<32, 48>(tasks, segs, tile_task, total_tiles, precision, s); break;
-    case 7: launch_cfg<96, 64>(tasks, segs, tile_task, total_tiles, precision, s); break;
-    case 8: launch_cfg<96, 32>(tasks, segs, tile_task, total_tiles, precision, s); break;
-    case 9: launch_cfg<64, 32>(tasks, segs, tile_task, total_tiles, precision, s); break;
+    case 0: launch_cfg<64, 64>(tasks, segs, tile_task, total_tiles, precision, s, off); break;
+    case 1: launch_cfg<32, 32>(tasks, segs, tile_task, total_tiles, precision, s, off); break;
+    case 2: launch_cfg<128, 32>(tasks, segs, tile_task, total_tiles, precision, s, off); break;
+    case 3: launch_cfg<64, 48>(tasks, segs, tile_task, total_tiles, precision, s, off); break;
+    case 4: launch_cfg<96, 48>(tasks, segs, tile_task, total_tiles, precision, s, off); break;
+    case 5: launch_cfg<128, 48>(tasks, segs, tile_task, total_tiles, precision, s, off); break;
+    case 6: launch_cfg<32, 48>(tasks, segs, tile_task, total_tiles, precision, s, off); break;
+    case 7: launch_cfg<96, 64>(tasks, segs, tile_task, total_tiles, precision, s, off); break;
+    case 8: launch_cfg<96, 32>(tasks, segs, tile_task, total_tiles, precision, s, off); break;
+    case 9: launch_cfg<64, 32>(tasks, segs, tile_task, total_tiles, precision, s, off); break;
     default: throw Error(TDMPS_ERR_ARG, "bad GEMM tile configuration");
   }
   check(hipGetLastError(), "gemm launch");

@@ -100,8 +100,9 @@ void dev_event_record(void* e, void* stream);
 float dev_event_elapsed_ms(void* a, void* b);  // synchronises on b
 
 // launchers (all asynchronous on `stream`)
+// Runs tiles tile_offset .. tile_offset + total_tiles - 1 of the tile table.
 void launch_gemm(const GemmTask* tasks, const GemmSeg* segs, const int32_t* tile_task, int64_t total_tiles, int cfg,
-                 int precision, void* stream);
+                 int precision, void* stream, int64_t tile_offset = 0);
 void launch_reduce(const ReduceTask* tasks, int ntasks, void* stream);
 constexpr int GEMM_NCFG = 10;  // tile shape configurations of launch_gemm
 int gemm_tile_m(int cfg);

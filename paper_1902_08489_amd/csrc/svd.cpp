@@ -446,7 +446,7 @@ void right_canonicalize(Contractor& C, Mps* m, double cutoff) {
         gp.add_seg(m->site[i - 1].c() + ol.panel_off[a] + ol.col[a][n], 0, 0, ol.width[a], OP_N, US.c() + us_off[sn],
                    0, 0, nb.dim[sn], OP_N, l.dim[so], 1, cplx{1, 0});
       }
-    gp.run(C.ctx, TDMPS_FP64);
+    gp.run(C.ctx, TDMPS_FP64, C.batched);
     m->bond[i] = nb;
     m->lay[i] = nl;
     m->lay[i - 1] = pl;

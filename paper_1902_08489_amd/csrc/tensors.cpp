@@ -265,6 +265,8 @@ void GemmPlan::finalize(Ctx* ctx) {
     }
     ntask[cfg] = (int)sel.size();
     ntiles[cfg] = base;
+    htile_base[cfg].clear();
+    for (auto& t : sel) htile_base[cfg].push_back(t.tile_base);
     if (sel.empty()) continue;
     dtasks[cfg] = DevBuf(sel.size() * sizeof(GemmTask));
     dev_h2d(dtasks[cfg].p, sel.data(), sel.size() * sizeof(GemmTask), ctx->stream);
@@ -278,19 +280,30 @@ void GemmPlan::finalize(Ctx* ctx) {
   }
 }
 
-void GemmPlan::launch(Ctx* ctx, int precision) {
-  for (int cfg = 0; cfg < NCFG; ++cfg)
-    if (ntask[cfg] > 0)
+void GemmPlan::launch(Ctx* ctx, int precision, bool batched) {
+  for (int cfg = 0; cfg < NCFG; ++cfg) {
+    if (ntask[cfg] <= 0) continue;
+    if (batched) {
       launch_gemm((const GemmTask*)dtasks[cfg].p, (const GemmSeg*)dsegs.p, (const int32_t*)dtile[cfg].p, ntiles[cfg],
-                  cfg, precision, ctx->stream);
+                  cfg, precision, ctx->stream, 0);
+    } else {
+      // one launch per task: the grid covers the task's own tiles only
+      for (size_t t = 0; t < htile_base[cfg].size(); ++t) {
+        const int64_t b0 = htile_base[cfg][t];
+        const int64_t b1 = t + 1 < htile_base[cfg].size() ? htile_base[cfg][t + 1] : ntiles[cfg];
+        launch_gemm((const GemmTask*)dtasks[cfg].p, (const GemmSeg*)dsegs.p, (const int32_t*)dtile[cfg].p, b1 - b0,
+                    cfg, precision, ctx->stream, b0);
+      }
+    }
+  }
   if (nred_tasks > 0) launch_reduce((const ReduceTask*)dred.p, nred_tasks, ctx->stream);
 }
 
-void GemmPlan::run(Ctx* ctx, int precision) {
+void GemmPlan::run(Ctx* ctx, int precision, bool batched) {
   const double t0 = wall_seconds();
   finalize(ctx);
   host_s += wall_seconds() - t0;
-  launch(ctx, precision);
+  launch(ctx, precision, batched);
   dev_sync(ctx->stream);
 }
 

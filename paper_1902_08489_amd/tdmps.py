@@ -62,6 +62,7 @@ _SIGS = {
     "tdmps_ctx_destroy": (ct.c_int32, [_P]),
     "tdmps_ctx_counters": (ct.c_int32, [_P, _D]),
     "tdmps_ctx_reset_counters": (ct.c_int32, [_P]),
+    "tdmps_ctx_set_launch_mode": (ct.c_int32, [_P, ct.c_int32]),
     "tdmps_mpo_from_integrals": (ct.c_int32, [_P, ct.c_int32, _D, _D, ct.c_double, _PP]),
     "tdmps_mpo_one_body": (ct.c_int32, [_P, ct.c_int32, _D, _PP]),
     "tdmps_mpo_set_one_body": (ct.c_int32, [_P, _D]),
@@ -150,6 +151,10 @@ class Context:
 
     def reset_counters(self):
         _check(_LIB.tdmps_ctx_reset_counters(self.h))
+
+    def set_launch_mode(self, batched):
+        """1: grouped launch per contraction stage (default); 0: one launch per block product."""
+        _check(_LIB.tdmps_ctx_set_launch_mode(self.h, int(batched)))
 
     def close(self):
         if self.h:

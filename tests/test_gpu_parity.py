@@ -239,3 +239,15 @@ def test_deterministic_repeat(ctx, sys8):
     a, _ = T.apply_H(sys8.mpo, 1.0, psi, [], prm)
     b, _ = T.apply_H(sys8.mpo, 1.0, psi, [], prm)
     assert np.array_equal(a.get_blocks(), b.get_blocks())
+
+
+def test_per_block_launches_reproduce_grouped_launch(ctx, sys6):
+    """Batching baseline: one launch per block product gives bit-identical results (same tiles,
+    same fixed split-K order) to the grouped launches."""
+    psi = T.MPS.from_determinant(ctx, sys6.occ)
+    outs = []
+    for batched in (1, 0):
+        prm = T.fit_params(Dmax=100, n_sweeps=2, batched=batched)
+        out, _ = T.apply_H(sys6.mpo, 1.0, psi, params=prm)
+        outs.append(dense(out))
+    assert np.array_equal(outs[0], outs[1])
