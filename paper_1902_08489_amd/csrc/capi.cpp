@@ -1,6 +1,7 @@
 // C ABI: contexts, states, operations, time steps and the kernel-level H_eff handle.
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 
@@ -27,6 +28,7 @@ struct tdmps_heff_s {
 namespace {
 
 Contractor make_contractor(Ctx* ctx, const tdmps_fit_params* prm) {
+  dev_bind(ctx->device, ctx->stream);
   Contractor C;
   C.ctx = ctx;
   if (prm) {
@@ -92,6 +94,8 @@ extern "C" tdmps_status tdmps_ctx_create(int32_t device, void* hip_stream, tdmps
       c->stream = dev_stream_create();
       c->own_stream = true;
     }
+    c->phase_sync = std::getenv("TDMPS_PHASE_TIMING") != nullptr;
+    dev_bind(device, c->stream);
     *out = c;
   });
 }
@@ -480,6 +484,7 @@ extern "C" tdmps_status tdmps_heff_apply(tdmps_heff h, const void* in, void* out
   return guard([&] {
     TDMPS_REQUIRE(h && in && out, TDMPS_ERR_ARG, "NULL argument");
     TDMPS_REQUIRE(in != out, TDMPS_ERR_ARG, "in-place apply is not supported");
+    dev_bind(h->ctx->device, h->ctx->stream);
     if (!h->plan || h->last_in != in || h->last_out != out) {
       tdmps_fit_params prm{};
       prm.precision = h->precision;

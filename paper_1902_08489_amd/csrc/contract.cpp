@@ -448,7 +448,7 @@ void heff_apply(Contractor& C, const SideOps& lops, const SideOps& rops, const c
   auto plan = heff_plan(C, lops, rops, theta_in, kl, ket_l, ket_r, theta_out, bl, bra_l, bra_r, alpha, accumulate);
   C.t_plan += wall_seconds() - t0;
   plan->launch(C.ctx, C.precision, C.batched);
-  dev_sync(C.ctx->stream);
+  if (C.ctx->phase_sync) dev_sync(C.ctx->stream);
   C.heff_flops += plan->p1.flops + plan->p2.flops;
   if (alg_flops) *alg_flops = plan->alg_flops;
   C.t_heff += wall_seconds() - t0;

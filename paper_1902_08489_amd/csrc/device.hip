@@ -1,6 +1,8 @@
 // HIP runtime layer: device selection, a caching device allocator, copies, streams,
-// events and fill kernels.  All device memory of the library is ordered on the stream of
-// its context, so a freed block can be handed to later work on that stream at once.
+// events and fill kernels.  All device work of a context is ordered on its stream and the
+// host does not wait for it before releasing buffers, so a freed block is only handed to
+// later allocations bound to the same (device, stream): work queued after the release on that
+// stream runs after every earlier use of the block.
 #include <hip/hip_runtime.h>
 
 #include <map>
@@ -18,9 +20,19 @@ void check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw Error(TDMPS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+struct Key {
+  int device;
+  void* stream;
+  bool operator<(const Key& o) const { return device != o.device ? device < o.device : stream < o.stream; }
+};
+struct Block {
+  size_t size;
+  Key key;
+};
 std::mutex g_mu;
-std::multimap<size_t, void*> g_free;
-std::unordered_map<void*, size_t> g_size;
+std::map<Key, std::multimap<size_t, void*>> g_free;
+std::unordered_map<void*, Block> g_block;
+thread_local Key tl_key{0, nullptr};  // set by dev_bind
 
 size_t round_size(size_t b) {
   if (b < (1u << 20)) return (b + 511) & ~size_t(511);
@@ -28,10 +40,11 @@ size_t round_size(size_t b) {
 }
 
 void release_cache() {
-  for (auto& kv : g_free) {
-    g_size.erase(kv.second);
-    (void)hipFree(kv.second);
-  }
+  for (auto& lst : g_free)
+    for (auto& kv : lst.second) {
+      g_block.erase(kv.second);
+      (void)hipFree(kv.second);
+    }
   g_free.clear();
 }
 
@@ -55,13 +68,19 @@ __global__ void scale_kernel(double2* x, int64_t n, double ar, double ai) {
 
 void dev_set_device(int device) { check(hipSetDevice(device), "hipSetDevice"); }
 
+void dev_bind(int device, void* stream) {
+  tl_key = Key{device, stream};
+  dev_set_device(device);
+}
+
 void* dev_alloc(size_t bytes) {
   size_t b = round_size(bytes);
   std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_free.lower_bound(b);
-  if (it != g_free.end() && it->first <= b + b / 4 + (4u << 20)) {
+  auto& lst = g_free[tl_key];
+  auto it = lst.lower_bound(b);
+  if (it != lst.end() && it->first <= b + b / 4 + (4u << 20)) {
     void* p = it->second;
-    g_free.erase(it);
+    lst.erase(it);
     return p;
   }
   void* p = nullptr;
@@ -74,16 +93,16 @@ void* dev_alloc(size_t bytes) {
       return nullptr;
     }
   }
-  g_size[p] = b;
+  g_block[p] = Block{b, tl_key};
   return p;
 }
 
 void dev_free(void* p) {
   if (!p) return;
   std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_size.find(p);
-  if (it == g_size.end()) return;
-  g_free.emplace(it->second, p);
+  auto it = g_block.find(p);
+  if (it == g_block.end()) return;
+  g_free[it->second.key].emplace(it->second.size, p);
 }
 
 void dev_h2d(void* dst, const void* src, size_t bytes, void* stream) {

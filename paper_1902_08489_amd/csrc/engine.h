@@ -106,6 +106,11 @@ struct tdmps_ctx_s {
   void* ev[2] = {nullptr, nullptr};
   double counters[TDMPS_NCOUNTERS] = {0};
   int batched = 1;  // launch mode of the H_eff handle API (tdmps_ctx_set_launch_mode)
+  // Work of a context is ordered on one stream, so the host synchronises only where it reads
+  // device data.  With phase_sync (environment variable TDMPS_PHASE_TIMING set at context
+  // creation) every contraction stage also ends in a synchronisation, so that the per-phase
+  // wall-clock counters measure device time (at the cost of host / device overlap).
+  bool phase_sync = false;
   bool timing = false;
 };
 

@@ -85,6 +85,9 @@ struct QrMat {
 
 // runtime
 void dev_set_device(int device);
+// Binds the calling thread to (device, stream): later allocations are served from blocks
+// released on that stream (or fresh ones).
+void dev_bind(int device, void* stream);
 void* dev_alloc(size_t bytes);  // returns nullptr when out of memory
 void dev_free(void* p);
 void dev_h2d(void* dst, const void* src, size_t bytes, void* stream);

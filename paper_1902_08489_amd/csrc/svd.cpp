@@ -146,7 +146,7 @@ struct SvdBatch {
       launch_qr_apply(dq, nm, cblocks, j0, 0, ctx->stream);
     }
     launch_qr_rt(dq, nm, ctx->stream);
-    dev_sync(ctx->stream);
+    if (ctx->phase_sync) dev_sync(ctx->stream);
     t_qr = wall_seconds() - tq;
     const SvdMat* dm = st.put(ctx, xm);
     launch_svd_init(dm, nm, ctx->stream);

@@ -304,7 +304,7 @@ void GemmPlan::run(Ctx* ctx, int precision, bool batched) {
   finalize(ctx);
   host_s += wall_seconds() - t0;
   launch(ctx, precision, batched);
-  dev_sync(ctx->stream);
+  if (ctx->phase_sync) dev_sync(ctx->stream);
 }
 
 void CopyPlan::add(const cplx* src, int64_t src_rs, int64_t src_cs, cplx* dst, int dst_ld, int rows, int cols, int flags,
@@ -331,12 +331,13 @@ void CopyPlan::run(Ctx* ctx) {
   Staging st;
   const CopyTask* d = st.put(ctx, tasks);
   launch_copy(d, (int)tasks.size(), ctx->stream);
-  dev_sync(ctx->stream);
+  if (ctx->phase_sync) dev_sync(ctx->stream);
 }
 
 // ---------------------------------------------------------------- states
 Mps* mps_new(Ctx* ctx, int L, const std::vector<Bond>& bonds) {
   TDMPS_REQUIRE((int)bonds.size() == L + 1, TDMPS_ERR_ARG, "need L+1 bonds");
+  dev_bind(ctx->device, ctx->stream);
   auto* m = new Mps();
   try {
     m->ctx = ctx;
@@ -362,6 +363,7 @@ Mps* mps_new(Ctx* ctx, int L, const std::vector<Bond>& bonds) {
 }
 
 Mps* mps_clone(const Mps* src) {
+  dev_bind(src->ctx->device, src->ctx->stream);
   auto* m = new Mps();
   try {
     m->ctx = src->ctx;
@@ -387,7 +389,6 @@ void mps_from_det(Mps* m, const uint8_t* occ) {
     TDMPS_REQUIRE(m->lay[i].size == 1, TDMPS_ERR_ARG, "determinant layout");
     dev_h2d(m->site[i].p, one.data(), sizeof(cplx), m->ctx->stream);
   }
-  dev_sync(m->ctx->stream);
 }
 
 MpoHost identity_mpo(int L) {
@@ -416,7 +417,6 @@ MpoHost identity_mpo(int L) {
 
 void scale_mps(Ctx* ctx, Mps* m, cplx alpha) {
   if (m->lay[0].size) launch_scale(m->site[0].c(), m->lay[0].size, alpha, ctx->stream);
-  dev_sync(ctx->stream);
 }
 
 }  // namespace tdmps
