@@ -110,10 +110,33 @@ tdmps_status tdmps_ctx_destroy(tdmps_ctx ctx);
 tdmps_status tdmps_ctx_counters(tdmps_ctx ctx, double* out);
 tdmps_status tdmps_ctx_reset_counters(tdmps_ctx ctx);
 /* Launch mode of tdmps_heff_apply (Batching row of the benchmark set): 1 = every block product
- * of a contraction stage in one grouped launch per tile shape (default); 0 = one kernel
- * launch per block product, the per-block baseline.  Fits and time steps take the mode from
- * tdmps_fit_params.batched instead. */
+ * of a contraction stage in one grouped launch per tile shape (default); 2 = the same grouped
+ * launches recorded once per (plan, input, output) into a HIP graph on the context stream and
+ * replayed as one graph launch afterwards (the context stream must then be a non-default
+ * stream: contexts created with a NULL stream own one); 0 = one kernel launch per block
+ * product, the per-block baseline.  All three give bit-identical results.  Fits and time
+ * steps take the grouped/per-block choice from tdmps_fit_params.batched instead.
+ * TDMPS_ERR_ARG for other values. */
 tdmps_status tdmps_ctx_set_launch_mode(tdmps_ctx ctx, int32_t batched);
+/* Tile shapes of the grouped block GEMM (Batching row).  There are TDMPS_TILE_CONFIGS shapes
+ * (complex rows x columns: 64x64, 32x32, 128x32, 64x48, 96x48, 128x48, 32x48, 96x64, 96x32,
+ * 64x32).  By default a task's shape is chosen by a padding / throughput cost model.
+ * tdmps_ctx_autotune times every shape on synthetic grouped products for each bucket of
+ * (rows, columns, total reduction length) at one precision and makes plans built afterwards
+ * take the fastest shape of their task's bucket.  Buckets: rows and columns by the first of
+ * 16, 32, 48, 64, 96, 128, 192, 256 that is >= the size (larger sizes in the last bucket);
+ * reduction length by the first of 64, 512, 4096 (same rule).  cfg_out (int32) and
+ * tflops_out (measured TFLOP/s of the chosen shape), both nullable, receive
+ * TDMPS_TILE_BUCKETS entries in (rows, columns, reduction) row-major order.  Takes a few
+ * seconds and ~300 MiB of device memory; results do not depend on the tile shape.
+ * tdmps_ctx_set_tile_config forces one shape (0..TDMPS_TILE_CONFIGS-1) for every task, -1
+ * returns to the tuned table or the cost model; tdmps_ctx_clear_tuning drops tuned tables.
+ * Plans made before any of these calls are rebuilt on their next use. */
+#define TDMPS_TILE_CONFIGS 10
+#define TDMPS_TILE_BUCKETS 192
+tdmps_status tdmps_ctx_autotune(tdmps_ctx ctx, int32_t precision, int32_t* cfg_out, double* tflops_out);
+tdmps_status tdmps_ctx_set_tile_config(tdmps_ctx ctx, int32_t cfg);
+tdmps_status tdmps_ctx_clear_tuning(tdmps_ctx ctx);
 
 /* ---------------------------------------------------------------- Hamiltonian MPO
  * Exact MPO of Eq. (hamil): H = sum_pq h_pq a+_{p s} a_{q s}

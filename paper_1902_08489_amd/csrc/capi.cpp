@@ -23,6 +23,9 @@ struct tdmps_heff_s {
   void* last_out = nullptr;
   double alg_flops = 0;
   const MpoHost* H = nullptr;
+  int plan_gen = -1;     // tile-rule generation the plan was made under
+  void* graph = nullptr;  // captured launch sequence of the plan (launch mode 2)
+  ~tdmps_heff_s() { tdmps::graph_destroy(graph); }
 };
 
 namespace {
@@ -119,8 +122,48 @@ extern "C" tdmps_status tdmps_ctx_counters(tdmps_ctx ctx, double* out) {
 extern "C" tdmps_status tdmps_ctx_set_launch_mode(tdmps_ctx ctx, int32_t batched) {
   return guard([&] {
     TDMPS_REQUIRE(ctx, TDMPS_ERR_ARG, "NULL argument");
-    TDMPS_REQUIRE(batched == 0 || batched == 1, TDMPS_ERR_ARG, "launch mode must be 0 or 1");
+    TDMPS_REQUIRE(batched >= 0 && batched <= 2, TDMPS_ERR_ARG, "launch mode must be 0, 1 or 2");
     ctx->batched = batched;
+  });
+}
+
+static_assert(TDMPS_TILE_CONFIGS == GEMM_NCFG, "tile configuration count");
+static_assert(TDMPS_TILE_BUCKETS == TILE_NB * TILE_NB * TILE_NK, "tile bucket count");
+
+extern "C" tdmps_status tdmps_ctx_set_tile_config(tdmps_ctx ctx, int32_t cfg) {
+  return guard([&] {
+    TDMPS_REQUIRE(ctx, TDMPS_ERR_ARG, "NULL argument");
+    TDMPS_REQUIRE(cfg >= -1 && cfg < GEMM_NCFG, TDMPS_ERR_ARG, "tile configuration out of range");
+    ctx->tile_cfg = cfg;
+    ctx->tune_gen++;
+  });
+}
+
+extern "C" tdmps_status tdmps_ctx_autotune(tdmps_ctx ctx, int32_t precision, int32_t* cfg_out, double* tflops_out) {
+  return guard([&] {
+    TDMPS_REQUIRE(ctx, TDMPS_ERR_ARG, "NULL argument");
+    TDMPS_REQUIRE(precision == TDMPS_FP64 || precision == TDMPS_FP32 || precision == TDMPS_BF16X3, TDMPS_ERR_ARG,
+                  "unknown precision");
+    dev_bind(ctx->device, ctx->stream);
+    TileTable t;
+    autotune_tiles(ctx, precision, t);
+    ctx->tune[precision] = t;
+    ctx->tune_gen++;
+    int q = 0;
+    for (int a = 0; a < TILE_NB; ++a)
+      for (int b = 0; b < TILE_NB; ++b)
+        for (int c = 0; c < TILE_NK; ++c, ++q) {
+          if (cfg_out) cfg_out[q] = t.cfg[a][b][c];
+          if (tflops_out) tflops_out[q] = t.tflops[a][b][c];
+        }
+  });
+}
+
+extern "C" tdmps_status tdmps_ctx_clear_tuning(tdmps_ctx ctx) {
+  return guard([&] {
+    TDMPS_REQUIRE(ctx, TDMPS_ERR_ARG, "NULL argument");
+    for (auto& t : ctx->tune) t.valid = false;
+    ctx->tune_gen++;
   });
 }
 
@@ -485,16 +528,20 @@ extern "C" tdmps_status tdmps_heff_apply(tdmps_heff h, const void* in, void* out
     TDMPS_REQUIRE(h && in && out, TDMPS_ERR_ARG, "NULL argument");
     TDMPS_REQUIRE(in != out, TDMPS_ERR_ARG, "in-place apply is not supported");
     dev_bind(h->ctx->device, h->ctx->stream);
-    if (!h->plan || h->last_in != in || h->last_out != out) {
+    Ctx* c = h->ctx;
+    if (!h->plan || h->last_in != in || h->last_out != out || h->plan_gen != c->tune_gen) {
+      graph_destroy(h->graph);
+      h->graph = nullptr;
+      h->plan.reset();
       tdmps_fit_params prm{};
       prm.precision = h->precision;
-      Contractor C = make_contractor(h->ctx, &prm);
+      Contractor C = make_contractor(c, &prm);
       h->plan = heff_plan(C, *h->lops, *h->rops, (const cplx*)in, h->kl, h->ket_l, h->ket_r, (cplx*)out, h->bl,
                           h->bra_l, h->bra_r, cplx{1, 0}, false);
       h->last_in = in;
       h->last_out = out;
+      h->plan_gen = c->tune_gen;
       h->alg_flops = h->plan->alg_flops;
-      Ctx* c = h->ctx;
       c->counters[0] = h->alg_flops;
       c->counters[1] = h->plan->p1.flops;
       c->counters[2] = h->plan->p2.flops;
@@ -504,8 +551,24 @@ extern "C" tdmps_status tdmps_heff_apply(tdmps_heff h, const void* in, void* out
       c->counters[6] = (double)h->plan->p1.segs.size();
       c->counters[7] = (double)h->plan->p2.segs.size();
     }
-    h->plan->launch(h->ctx, h->precision, h->ctx->batched != 0);
-    dev_sync(h->ctx->stream);
+    if (c->batched == 2) {
+      if (!h->graph) {
+        // the plan's task tables were uploaded on this stream; capture only launches
+        dev_sync(c->stream);
+        graph_begin(c->stream);
+        try {
+          h->plan->launch(c, h->precision, true);
+        } catch (...) {
+          graph_abort(c->stream);
+          throw;
+        }
+        h->graph = graph_end(c->stream);
+      }
+      graph_launch(h->graph, c->stream);
+    } else {
+      h->plan->launch(c, h->precision, c->batched != 0);
+    }
+    dev_sync(c->stream);
   });
 }
 

@@ -638,8 +638,8 @@ std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const Si
         }
     plan->alg_flops = alg;
   }
-  p1.finalize(C.ctx);
-  p2.finalize(C.ctx);
+  p1.finalize(C.ctx, C.precision);
+  p2.finalize(C.ctx, C.precision);
   return plan;
 }
 

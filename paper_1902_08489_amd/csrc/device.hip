@@ -152,6 +152,35 @@ void* dev_stream_create() {
 
 void dev_stream_destroy(void* s) { (void)hipStreamDestroy((hipStream_t)s); }
 
+// HIP graphs: a launch sequence recorded once on a (non-default) stream and replayed.
+void graph_begin(void* stream) {
+  check(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+}
+
+void* graph_end(void* stream) {
+  hipGraph_t g = nullptr;
+  check(hipStreamEndCapture((hipStream_t)stream, &g), "hipStreamEndCapture");
+  hipGraphExec_t e = nullptr;
+  const hipError_t r = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  check(r, "hipGraphInstantiate");
+  return e;
+}
+
+void graph_abort(void* stream) {
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture((hipStream_t)stream, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+  (void)hipGetLastError();
+}
+
+void graph_launch(void* exec, void* stream) {
+  check(hipGraphLaunch((hipGraphExec_t)exec, (hipStream_t)stream), "hipGraphLaunch");
+}
+
+void graph_destroy(void* exec) {
+  if (exec) (void)hipGraphExecDestroy((hipGraphExec_t)exec);
+}
+
 void* dev_event_create() {
   hipEvent_t e;
   check(hipEventCreate(&e), "hipEventCreate");

@@ -97,6 +97,30 @@ struct TwoLayout {
 
 inline Charge pair_charge(int n) { return local_charge(n >> 2) + local_charge(n & 3); }
 
+// Measured tile shape per block-size bucket of the grouped GEMM (tdmps_ctx_autotune).
+// Buckets: output rows and columns by TILE_EDGES (the first edge >= the size), total complex
+// reduction length per output by TILE_KEDGES.
+constexpr int TILE_NB = 8, TILE_NK = 3;
+constexpr int TILE_EDGES[TILE_NB] = {16, 32, 48, 64, 96, 128, 192, 256};
+constexpr int TILE_KEDGES[TILE_NK] = {64, 512, 4096};
+struct TileTable {
+  bool valid = false;
+  int8_t cfg[TILE_NB][TILE_NB][TILE_NK] = {};
+  float tflops[TILE_NB][TILE_NB][TILE_NK] = {};  // rate of the chosen shape in the tuning run
+};
+inline int tile_bucket(int64_t x) {
+  for (int i = 0; i < TILE_NB; ++i)
+    if (x <= TILE_EDGES[i]) return i;
+  return TILE_NB - 1;
+}
+inline int tile_kbucket(int64_t k) {
+  for (int i = 0; i < TILE_NK; ++i)
+    if (k <= TILE_KEDGES[i]) return i;
+  return TILE_NK - 1;
+}
+// Times every tile shape on synthetic grouped products of each bucket and fills t.
+void autotune_tiles(struct ::tdmps_ctx_s* ctx, int precision, TileTable& t);
+
 }  // namespace tdmps
 
 struct tdmps_ctx_s {
@@ -105,7 +129,14 @@ struct tdmps_ctx_s {
   bool own_stream = false;
   void* ev[2] = {nullptr, nullptr};
   double counters[TDMPS_NCOUNTERS] = {0};
-  int batched = 1;  // launch mode of the H_eff handle API (tdmps_ctx_set_launch_mode)
+  // launch mode of the H_eff handle API (tdmps_ctx_set_launch_mode): 0 = one launch per block
+  // product, 1 = grouped launches, 2 = grouped launches captured once into a HIP graph and replayed
+  int batched = 1;
+  // Tile shape of the grouped GEMM: tile_cfg >= 0 forces one configuration for every task;
+  // otherwise a tuned table (tdmps_ctx_autotune) is used where present, else the cost model.
+  int tile_cfg = -1;
+  tdmps::TileTable tune[3];
+  int tune_gen = 0;  // bumped whenever the tile choice rules change (plans made before are stale)
   // Work of a context is ordered on one stream, so the host synchronises only where it reads
   // device data.  With phase_sync (environment variable TDMPS_PHASE_TIMING set at context
   // creation) every contraction stage also ends in a synchronisation, so that the per-phase
@@ -200,7 +231,7 @@ struct GemmPlan {
   int ntask[NCFG] = {};
   int64_t ntiles[NCFG] = {};
   bool final_ = false;
-  void finalize(Ctx* ctx);
+  void finalize(Ctx* ctx, int precision);
   // batched: one grouped launch per tile shape (default); else one launch per task (the
   // per-block baseline the grouped launch is compared with)
   void launch(Ctx* ctx, int precision, bool batched = true);

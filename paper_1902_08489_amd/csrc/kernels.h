@@ -101,6 +101,13 @@ void* dev_event_create();
 void dev_event_destroy(void* e);
 void dev_event_record(void* e, void* stream);
 float dev_event_elapsed_ms(void* a, void* b);  // synchronises on b
+// Stream capture into a HIP graph (the stream must not be the legacy default stream; the
+// captured work must hold no allocations, synchronisations or memset nodes).
+void graph_begin(void* stream);
+void* graph_end(void* stream);    // instantiated graph
+void graph_abort(void* stream);   // ends a failed capture and drops it
+void graph_launch(void* exec, void* stream);
+void graph_destroy(void* exec);
 
 // launchers (all asynchronous on `stream`)
 // Runs tiles tile_offset .. tile_offset + total_tiles - 1 of the tile table.

@@ -142,7 +142,7 @@ void GemmPlan::add_seg(const cplx* A, int64_t bsA, int64_t rsA, int lda, int opA
   flops += 8.0 * t.m * (double)t.n * k * nred * t.nbatch;
 }
 
-void GemmPlan::finalize(Ctx* ctx) {
+void GemmPlan::finalize(Ctx* ctx, int precision) {
   if (final_) return;
   final_ = true;
   // drop tasks without work that do not need to overwrite their output
@@ -232,12 +232,20 @@ void GemmPlan::finalize(Ctx* ctx) {
     dsegs = DevBuf(nsegs.size() * sizeof(GemmSeg));
     dev_h2d(dsegs.p, nsegs.data(), nsegs.size() * sizeof(GemmSeg), ctx->stream);
   }
-  // tile shape per task: 64x64 for wide outputs, 128x32 for tall narrow ones (the
-  // channel-stacked L*theta products), 32x32 otherwise
-  // Tile shape per task: least padded MFMA work divided by the shape's relative throughput
-  // (measured on aligned shapes with enough tiles to fill the chip, FP64).
+  // Tile shape per task: a forced shape (tdmps_ctx_set_tile_config), else the measured best
+  // shape of the task's bucket (tdmps_ctx_autotune), else the least padded MFMA work divided
+  // by the shape's relative throughput (measured on aligned shapes with enough tiles to fill
+  // the chip, FP64).
   static const double eff[GEMM_NCFG] = {1.0, 0.92, 0.9, 0.96, 0.82, 0.8, 0.94, 0.85, 0.8, 0.97};
-  auto pick = [](const GemmTask& t) {
+  const TileTable* tt_tab = (precision >= 0 && precision < 3 && ctx->tune[precision].valid) ? &ctx->tune[precision]
+                                                                                           : nullptr;
+  auto pick = [&](const GemmTask& t) {
+    if (ctx->tile_cfg >= 0) return ctx->tile_cfg;
+    if (tt_tab) {
+      int64_t k = 0;
+      for (int s = t.seg0; s < t.seg0 + t.nseg; ++s) k += (int64_t)nsegs[s].nred * nsegs[s].k;
+      return (int)tt_tab->cfg[tile_bucket(t.m)][tile_bucket(t.n)][tile_kbucket(k)];
+    }
     int best = 0;
     double bc = 1e300;
     for (int c = 0; c < NCFG; ++c) {
@@ -251,12 +259,15 @@ void GemmPlan::finalize(Ctx* ctx) {
     }
     return best;
   };
+  std::vector<int> choice(out.size());
+  for (size_t i = 0; i < out.size(); ++i) choice[i] = pick(out[i]);
   for (int cfg = 0; cfg < NCFG; ++cfg) {
     std::vector<GemmTask> sel;
     int64_t base = 0;
     int tm = gemm_tile_m(cfg), tn = gemm_tile_n(cfg);
-    for (auto t : out) {
-      if (pick(t) != cfg) continue;
+    for (size_t i = 0; i < out.size(); ++i) {
+      if (choice[i] != cfg) continue;
+      GemmTask t = out[i];
       t.tiles_m = (t.m + tm - 1) / tm;
       t.tiles_n = (t.n + tn - 1) / tn;
       t.tile_base = base;
@@ -301,7 +312,7 @@ void GemmPlan::launch(Ctx* ctx, int precision, bool batched) {
 
 void GemmPlan::run(Ctx* ctx, int precision, bool batched) {
   const double t0 = wall_seconds();
-  finalize(ctx);
+  finalize(ctx, precision);
   host_s += wall_seconds() - t0;
   launch(ctx, precision, batched);
   if (ctx->phase_sync) dev_sync(ctx->stream);

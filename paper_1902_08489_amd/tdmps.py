@@ -55,6 +55,8 @@ _I64 = ct.POINTER(ct.c_int64)
 _U8 = ct.POINTER(ct.c_uint8)
 
 NCOUNTERS = 20  # TDMPS_NCOUNTERS of include/tdmps.h
+TILE_CONFIGS = 10  # TDMPS_TILE_CONFIGS
+TILE_BUCKETS = 192  # TDMPS_TILE_BUCKETS
 
 _SIGS = {
     "tdmps_last_error": (ct.c_char_p, []),
@@ -63,6 +65,9 @@ _SIGS = {
     "tdmps_ctx_counters": (ct.c_int32, [_P, _D]),
     "tdmps_ctx_reset_counters": (ct.c_int32, [_P]),
     "tdmps_ctx_set_launch_mode": (ct.c_int32, [_P, ct.c_int32]),
+    "tdmps_ctx_set_tile_config": (ct.c_int32, [_P, ct.c_int32]),
+    "tdmps_ctx_autotune": (ct.c_int32, [_P, ct.c_int32, _I32, _D]),
+    "tdmps_ctx_clear_tuning": (ct.c_int32, [_P]),
     "tdmps_mpo_from_integrals": (ct.c_int32, [_P, ct.c_int32, _D, _D, ct.c_double, _PP]),
     "tdmps_mpo_one_body": (ct.c_int32, [_P, ct.c_int32, _D, _PP]),
     "tdmps_mpo_set_one_body": (ct.c_int32, [_P, _D]),
@@ -153,8 +158,24 @@ class Context:
         _check(_LIB.tdmps_ctx_reset_counters(self.h))
 
     def set_launch_mode(self, batched):
-        """1: grouped launch per contraction stage (default); 0: one launch per block product."""
+        """1: grouped launch per contraction stage (default); 2: grouped launches replayed from a
+        captured HIP graph; 0: one launch per block product."""
         _check(_LIB.tdmps_ctx_set_launch_mode(self.h, int(batched)))
+
+    def set_tile_config(self, cfg):
+        """Force one grouped-GEMM tile shape (0..TILE_CONFIGS-1); -1 restores the automatic choice."""
+        _check(_LIB.tdmps_ctx_set_tile_config(self.h, int(cfg)))
+
+    def autotune(self, precision=FP64):
+        """Times every tile shape per block-size bucket; returns (cfg, tflops) arrays of shape
+        (8, 8, 3) over (row bucket, column bucket, reduction bucket)."""
+        cfg = np.zeros(TILE_BUCKETS, dtype=np.int32)
+        tf = np.zeros(TILE_BUCKETS)
+        _check(_LIB.tdmps_ctx_autotune(self.h, int(precision), cfg.ctypes.data_as(_I32), _dp(tf)))
+        return cfg.reshape(8, 8, 3), tf.reshape(8, 8, 3)
+
+    def clear_tuning(self):
+        _check(_LIB.tdmps_ctx_clear_tuning(self.h))
 
     def close(self):
         if self.h:
