@@ -70,6 +70,9 @@ def main():
     ap.add_argument("--check", type=int, default=8, help="sampled outputs checked against Slater-Condon")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-block", type=int, default=1, help="also time one launch per block product (baseline)")
+    ap.add_argument("--tune", type=int, default=1, help="run the tile-shape autotuner before timing")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="copy 1 GiB device to device once before timing (reference for HBM byte counters)")
     ap.add_argument("--L", type=int, default=24)
     ap.add_argument("--D", type=int, default=1024)
     args = ap.parse_args()
@@ -77,6 +80,9 @@ def main():
         print("bench.py measures one GPU: the contraction path is single-device (multi-GPU sharding over MPO "
               "channels is a design note only); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    def progress(msg):
+        print(f"bench: {msg}", file=sys.stderr, flush=True)
 
     import torch
     import synth
@@ -93,8 +99,10 @@ def main():
     mpo = T.MPO.from_integrals(ctx, h, eri, 0.0)
     bonds, data, S, Tset = synth.det_basis_state(L, Nu, Nd, D, sigma=1.0, seed=L)
     st = T.MPS.from_blocks(ctx, bonds, data)
+    progress("state built")
     op = T.Heff(mpo, st, st, c, precision=PREC[args.precision])
     tot, blocks = op.layout(0)
+    progress("environments built")
     rng = np.random.Generator(np.random.PCG64(L + 3))
     theta = rng.standard_normal(tot // 2) + 1j * rng.standard_normal(tot // 2)
     tin = torch.from_numpy(theta.view(np.float64).copy()).to("cuda")
@@ -120,20 +128,30 @@ def main():
     ctx.set_launch_mode(2)
     op.apply(tin.data_ptr(), tout.data_ptr())
     graph_ms, _ = timed(probe)
-    t_tune = time.perf_counter()
-    tune_cfg, _ = ctx.autotune(PREC[args.precision])
-    t_tune = time.perf_counter() - t_tune
-    op.apply(tin.data_ptr(), tout.data_ptr())
-    tuned_ms, _ = timed(probe)
-    tile_rule = "autotuned" if tuned_ms < graph_ms else "cost model"
-    if tile_rule != "autotuned":
-        ctx.clear_tuning()
+    tune_cfg, t_tune, tuned_ms, tile_rule = None, 0.0, None, "cost model"
+    if args.tune:
+        t_tune = time.perf_counter()
+        tune_cfg, _ = ctx.autotune(PREC[args.precision])
+        t_tune = time.perf_counter() - t_tune
+        op.apply(tin.data_ptr(), tout.data_ptr())
+        tuned_ms, _ = timed(probe)
+        tile_rule = "autotuned" if tuned_ms < graph_ms else "cost model"
+        progress(f"autotuned in {t_tune:.1f} s")
+        if tile_rule != "autotuned":
+            ctx.clear_tuning()
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         op.apply(tin.data_ptr(), tout.data_ptr())
     flops = op.flops()
     plan_stats = ctx.counters()
     ms_step, kms = timed(args.steps)
+    progress(f"timed {args.steps} applies: {ms_step:.2f} ms each")
     ms_kernel = float(np.mean(kms))
     value = flops / (ms_step * 1e-3) / 1e12
     achieved = flops / (ms_kernel * 1e-3) / 1e12
@@ -142,7 +160,8 @@ def main():
     # batching baseline: the same H_eff*theta with one kernel launch per block product
     batching = {"graph_ms": graph_ms, "grouped_eager_ms": grouped_ms, "graph_autotuned_ms": tuned_ms,
                 "tile_rule_timed": tile_rule, "autotune_seconds": t_tune,
-                "autotune_buckets_per_shape": np.bincount(tune_cfg.ravel(), minlength=T.TILE_CONFIGS).tolist()}
+                "autotune_buckets_per_shape": None if tune_cfg is None else
+                np.bincount(tune_cfg.ravel(), minlength=T.TILE_CONFIGS).tolist()}
     if args.per_block:
         ctx.set_launch_mode(0)
         op.apply(tin.data_ptr(), tout.data_ptr())

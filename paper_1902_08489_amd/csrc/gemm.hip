@@ -85,9 +85,16 @@ struct Cursor {
   }
 };
 
+// Operands are read through global-address-space pointers: generic (flat) loads would also
+// count against the LDS wait counter, so every LDS read of the MFMA loop would wait for the
+// prefetch of the next stage.
+typedef const __attribute__((address_space(1))) double* gptr;
+
 template <int BM, int BN, int BK>
 struct Stage {
-  // per-thread prefetch registers: ceil(BM*BK/256) A elements and ceil(BK*BN/256) B elements
+  // per-thread prefetch registers: ceil(BM*BK/256) A elements and ceil(BK*BN/256) B elements,
+  // raw as loaded (conjugation and the segment scale are applied when they are written to LDS,
+  // so that nothing waits for the loads before the MFMAs of the current stage are issued)
   static constexpr int NA = (BM * BK + 255) / 256;
   static constexpr int NB = (BK * BN + 255) / 256;
   static constexpr bool FULLA = BM * BK % 256 == 0;
@@ -95,6 +102,8 @@ struct Stage {
   double2 ra[NA], rb[NB];
 
   __device__ __forceinline__ void load(const Cursor& c, const GemmTask& T, int m0, int n0, int tid) {
+    const gptr A = (gptr)c.A;
+    const gptr B = (gptr)c.B;
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
       const int e = tid + q * 256;
@@ -109,9 +118,9 @@ struct Stage {
       const int gr = m0 + rr, gk = c.k0 + kk;
       double2 v = make_double2(0.0, 0.0);
       if ((FULLA || e < BM * BK) && gr < T.m && gk < c.K) {
-        v = c.tA ? c.A[(int64_t)gk * c.lda + gr] : c.A[(int64_t)gr * c.lda + gk];
-        if (c.cA) v.y = -v.y;
-        v = cmul(v, c.alpha);
+        const gptr p = A + 2 * (c.tA ? (int64_t)gk * c.lda + gr : (int64_t)gr * c.lda + gk);
+        v.x = p[0];
+        v.y = p[1];
       }
       ra[q] = v;
     }
@@ -129,8 +138,9 @@ struct Stage {
       const int gk = c.k0 + kk, gc = n0 + cc;
       double2 v = make_double2(0.0, 0.0);
       if ((FULLB || e < BK * BN) && gk < c.K && gc < T.n) {
-        v = c.tB ? c.B[(int64_t)gc * c.ldb + gk] : c.B[(int64_t)gk * c.ldb + gc];
-        if (c.cB) v.y = -v.y;
+        const gptr p = B + 2 * (c.tB ? (int64_t)gc * c.ldb + gk : (int64_t)gk * c.ldb + gc);
+        v.x = p[0];
+        v.y = p[1];
       }
       rb[q] = v;
     }
@@ -242,7 +252,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
           kk = e / BM;
           rr = e - kk * BM;
         }
-        const double2 v = st.ra[q];
+        double2 v = st.ra[q];
+        if (cur.cA) v.y = -v.y;
+        v = cmul(v, cur.alpha);
         if constexpr (PREC == P64) {
           *(double2*)&sm.A[rr][2 * kk] = v;
         } else if constexpr (PREC == P32) {
@@ -264,7 +276,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
           cc = e / BK;
           kk = e - cc * BK;
         }
-        const double2 v = st.rb[q];
+        double2 v = st.rb[q];
+        if (cur.cB) v.y = -v.y;
         if constexpr (PREC == P64) {
           *(double2*)&sm.B[2 * kk][2 * cc] = v;
           *(double2*)&sm.B[2 * kk + 1][2 * cc] = make_double2(-v.y, v.x);
@@ -340,26 +353,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
   // Epilogue.  Output lane layouts on gfx950 (read off the hardware): register e of lane l
   // holds row l/16 + 4e of a 16x16 tile for the f64 MFMA and row 4(l/16) + e for the f32
   // and bf16 MFMAs; column l%16 in all cases.
-  double2* C = (double2*)T.C + bidx * T.bsC;
+  typedef __attribute__((address_space(1))) double* gout;
+  const gout C = (gout)(T.C + bidx * T.bsC);
   const bool accum = T.flags & GEMM_ACCUM;
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int i = 0; i < TM; ++i) {
+    // one row group at a time: all previous values are loaded before any is needed, so the
+    // accumulating epilogue waits once per group instead of once per element
+    double old[TN][4];
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) old[j][e] = 0.0;
+    if (accum) {
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int rc = 2 * wn + j * 16 + l16;
+        const int gc = n0 + (rc >> 1);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = PREC == P64 ? lq + 4 * e : 4 * lq + e;
+          const int gr = m0 + wm + i * 16 + row;
+          if (gr < T.m && gc < T.n) old[j][e] = C[2 * ((int64_t)gr * T.ldc + gc) + (rc & 1)];
+        }
+      }
+    }
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int rc = 2 * wn + j * 16 + l16;
       const int gc = n0 + (rc >> 1);
-      const int part = rc & 1;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int row = PREC == P64 ? lq + 4 * e : 4 * lq + e;
         const int gr = m0 + wm + i * 16 + row;
-        if (gr < T.m && gc < T.n) {
-          double* p = (double*)(C + (int64_t)gr * T.ldc + gc) + part;
-          const double v = (double)acc[i][j][e];
-          *p = accum ? *p + v : v;
-        }
+        if (gr < T.m && gc < T.n) C[2 * ((int64_t)gr * T.ldc + gc) + (rc & 1)] = old[j][e] + (double)acc[i][j][e];
       }
     }
+  }
 }
 
 // Deterministic split-K reduction: C (+)= sum_s parts[s] in fixed order.
