@@ -10,8 +10,17 @@ in HBM.  Throughput is algorithmic TFLOP/s (8 flops per complex multiply-add of 
 products in the order (L theta) -> W -> (. R)), timed with HIP events on the library's
 stream.
 
+Other workloads of the benchmark set (each prints its own JSON line; not the default):
+  --workload krylov     Krylov time steps (default L = 16, D = 256, m = 10, dt = 0.05), steps/s
+                        and the per-step norm, energy and dipole
+  --workload precision  one Krylov step per precision (FP64, FP32, BF16 split) from the same
+                        state, per-step time and the relative change of norm, energy and
+                        dipole against the FP64 run (default L = 30, D = 1024)
+  --workload gradient   field-driven RK4 forward + adjoint backward for dD/dA
+                        (default L = 16, D = 256, 200 steps of 0.02, checkpoints every 20)
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32|bf16x3]
-       [--krylov 0|1] [--no-cpu-baseline] [--check N]
+       [--krylov 0|1] [--no-cpu-baseline] [--check N] [--workload heff|krylov|precision|gradient]
 """
 from __future__ import annotations
 
@@ -26,7 +35,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}  # dense TFLOP/s of the MFMA units used
+# Dense MFMA peaks (TFLOP/s) in algorithmic flops: the BF16 split runs three bf16 products
+# per real product, so its algorithmic peak is the bf16 rate (2500) over three.
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3}
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 
@@ -73,8 +84,14 @@ def main():
     ap.add_argument("--tune", type=int, default=1, help="run the tile-shape autotuner before timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device to device once before timing (reference for HBM byte counters)")
-    ap.add_argument("--L", type=int, default=24)
-    ap.add_argument("--D", type=int, default=1024)
+    ap.add_argument("--L", type=int, default=None)
+    ap.add_argument("--D", type=int, default=None)
+    ap.add_argument("--workload", default="heff", choices=["heff", "krylov", "precision", "gradient"])
+    ap.add_argument("--dt", type=float, default=None)
+    ap.add_argument("--sweeps", type=int, default=1, help="fit sweeps per H application (Krylov workloads)")
+    ap.add_argument("--rk4-steps", type=int, default=200)
+    ap.add_argument("--checkpoint", type=int, default=20)
+    ap.add_argument("--fd", type=int, default=0, help="gradient workload: also central finite differences")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the contraction path is single-device (multi-GPU sharding over MPO "
@@ -89,7 +106,9 @@ def main():
     from paper_1902_08489_amd import tdmps as T
 
     T.load()
-    L, D = args.L, args.D
+    if args.workload != "heff":
+        return other_workload(args, progress)
+    L, D = args.L or 24, args.D or 1024
     Nu, Nd = (L - 1) // 2, L // 2
     c = L // 2 - 1
     # the library's work runs on this (non-default) stream, and the events are recorded on it
@@ -253,6 +272,117 @@ def main():
                  "T_bytes": plan_stats[3], "tasks": [int(plan_stats[4]), int(plan_stats[5])],
                  "segments": [int(plan_stats[6]), int(plan_stats[7])]},
     }
+    print(json.dumps(line), flush=True)
+
+
+def other_workload(args, progress):
+    import torch
+    import synth
+    from paper_1902_08489_amd import tdmps as T
+
+    side = torch.cuda.Stream()
+    ctx = T.Context(0, stream=side.cuda_stream)
+    line = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "data": "synthetic (seeded integrals and block-sparse state)"}
+    if args.workload in ("krylov", "precision"):
+        L = args.L or (16 if args.workload == "krylov" else 30)
+        D = args.D or (256 if args.workload == "krylov" else 1024)
+        m = args.krylov_m if args.krylov_m != 12 or args.workload == "precision" else 10
+        dt = args.dt or 0.05
+        N0 = L if args.workload == "krylov" else 28
+        ell = 1.0 if args.workload == "krylov" else 2.0
+        Nu, Nd = (N0 - 1) // 2, N0 - 1 - (N0 - 1) // 2
+        h, eri, _ = synth.integrals(L, ell)
+        mu_pq = synth.dipole_matrix(L, ell)
+        H = T.MPO.from_integrals(ctx, h, eri, 0.0)
+        MU = T.MPO.one_body(ctx, mu_pq)
+        bk, dk = synth.random_state(L, Nu, Nd, D, sigma=1.0, seed=L + 5)
+        psi0 = T.MPS.from_blocks(ctx, bk, dk)
+        psi0.scale(1.0 / np.sqrt(T.overlap(psi0, psi0).real))
+        progress(f"L={L} D={D} state built")
+
+        def observables(psi):
+            n2 = T.overlap(psi, psi).real
+            return {"norm2": n2, "energy": T.expect(H, psi, psi).real / n2, "dipole": T.expect(MU, psi, psi).real / n2}
+
+        def run(prec, nsteps, warm):
+            prm = T.fit_params(Dmax=D, n_sweeps=args.sweeps, precision=PREC[prec])
+            psi = psi0
+            for _ in range(warm):
+                psi, _, _ = T.krylov_step(H, psi, dt, m, True, prm)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(nsteps):
+                psi, _, _ = T.krylov_step(H, psi, dt, m, True, prm)
+                progress(f"{prec} Krylov step {k + 1} of {nsteps}: {time.perf_counter() - t0:.1f} s")
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / nsteps, observables(psi)
+
+        os.environ["TDMPS_PROGRESS"] = "1"
+        if args.workload == "krylov":
+            sps, obs = run(args.precision, args.steps, args.warmup)
+            line.update({"metric": f"Krylov steps/s @L={L} D={D} m={m}", "value": 1.0 / sps, "unit": "steps/s",
+                         "ms_per_step": sps * 1e3, "dtype": args.precision,
+                         "config": {"workload": f"Krylov time step, L={L} N={N0 - 1} D={D} m={m} dt={dt}, "
+                                                f"{args.sweeps} sweep(s) per fit, from a random block state at full D",
+                                    "precision": args.precision},
+                         "observables_after": obs})
+        else:
+            res = {}
+            for prec in ("fp64", "fp32", "bf16x3"):
+                sps, obs = run(prec, args.steps, 0)
+                res[prec] = {"s_per_step": sps, **obs}
+            ref = res["fp64"]
+            for prec in ("fp32", "bf16x3"):
+                res[prec]["rel_err_vs_fp64"] = {k: abs(res[prec][k] - ref[k]) / abs(ref[k])
+                                                for k in ("norm2", "energy", "dipole")}
+            best = min(("fp32", "bf16x3"), key=lambda p: res[p]["s_per_step"])
+            line.update({"metric": f"Krylov steps/s @L={L} D={D}, mixed vs FP64", "value": 1.0 / res[best]["s_per_step"],
+                         "unit": "steps/s", "ms_per_step": res[best]["s_per_step"] * 1e3, "dtype": best,
+                         "config": {"workload": f"Krylov time step, L={L} N={N0 - 1} D={D} m={m} dt={dt}, "
+                                                f"{args.sweeps} sweep(s) per fit, from a random block state at full D"},
+                         "speedup_vs_fp64": ref["s_per_step"] / res[best]["s_per_step"], "per_precision": res})
+    else:
+        L = args.L or 16
+        D = args.D or 256
+        N0 = L
+        Nu, Nd = (N0 - 1) // 2, N0 - 1 - (N0 - 1) // 2
+        dt = args.dt or 0.02
+        h, eri, _ = synth.integrals(L, 1.0)
+        mu_pq = synth.dipole_matrix(L, 1.0)
+        H0 = T.MPO.from_integrals(ctx, h, eri, 0.0)
+        MU = T.MPO.one_body(ctx, mu_pq)
+        psi0 = T.MPS.from_determinant(ctx, synth.ionized_determinant(L, N0))
+        prm = T.fit_params(Dmax=D, n_sweeps=args.sweeps, precision=PREC[args.precision])
+        pulse = dict(omega=1.0, t_center=2.0, width=0.5)
+        A = 0.01
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tr = T.Trajectory(H0, h, mu_pq, MU, psi0, A, pulse["omega"], pulse["t_center"], pulse["width"], dt,
+                          args.rk4_steps, args.checkpoint, prm)
+        t_fwd = time.perf_counter() - t0
+        progress(f"forward {args.rk4_steps} RK4 steps: {t_fwd:.1f} s")
+        t0 = time.perf_counter()
+        g = tr.backward()
+        t_bwd = time.perf_counter() - t0
+        progress(f"backward: {t_bwd:.1f} s")
+        fd = None
+        if args.fd:
+            hA = 1e-4
+            vp = T.Trajectory(H0, h, mu_pq, MU, psi0, A + hA, pulse["omega"], pulse["t_center"], pulse["width"], dt,
+                              args.rk4_steps, args.checkpoint, prm).value
+            vm = T.Trajectory(H0, h, mu_pq, MU, psi0, A - hA, pulse["omega"], pulse["t_center"], pulse["width"], dt,
+                              args.rk4_steps, args.checkpoint, prm).value
+            fd = (vp - vm) / (2 * hA)
+        line.update({"metric": f"RK4 forward+adjoint steps/s @L={L} D={D}", "value": args.rk4_steps / (t_fwd + t_bwd),
+                     "unit": "steps/s", "ms_per_step": (t_fwd + t_bwd) / args.rk4_steps * 1e3,
+                     "dtype": args.precision,
+                     "config": {"workload": f"field-driven RK4, L={L} N={N0 - 1} D={D}, {args.rk4_steps} steps of {dt}, "
+                                            f"checkpoints every {args.checkpoint}, E(t) = A sin(t) exp(-(t-2)^2/0.5), "
+                                            f"A = {A}, {args.sweeps} sweep(s) per fit"},
+                     "forward_s": t_fwd, "backward_s": t_bwd, "dipole": tr.value, "dD_dA": g,
+                     "finite_difference": fd,
+                     "rel_diff_vs_fd": None if fd is None else abs(g - fd) / max(abs(fd), 1e-300)})
     print(json.dumps(line), flush=True)
 
 

@@ -7,7 +7,7 @@
  * (time_evo_opera)) with the Hamiltonian of Eq. (hamil), states stored as matrix
  * product states (Eq. (mps)), and the three MPS operations of the "Operations on MPS"
  * section -- scaling, addition and application of the Hamiltonian, both done by the
- * variational fit of Eq. (add_min) -- composed into RK4 (Eqs. (k1-k4), (rk_add)) and
+ * variational fit of Eq. (add_min) -- composed into RK4 (the RK4 stage definitions and Eq. (rk_add)) and
  * Krylov (Eqs. (kry_non), (kry_orth), (krylov_evo)) time steps.
  *
  * Conventions
@@ -204,7 +204,7 @@ tdmps_status tdmps_mps_compress(int32_t nterms, const double* beta, const tdmps_
  * row-major) may be NULL.  Returns TDMPS_ERR_SINGULAR if N is not positive definite. */
 tdmps_status tdmps_krylov_step(tdmps_mpo H, tdmps_mps psi, double dt, int32_t m, int32_t flags,
                                const tdmps_fit_params* prm, tdmps_mps* out, double* Nmat, double* Hmat);
-/* RK4 step (Eqs. (k1-k4), (rk_add)) with k_s = -i dt H(t_s) u_s fitted, u_s compressed:
+/* RK4 step (the RK4 stage definitions and Eq. (rk_add)) with k_s = -i dt H(t_s) u_s fitted, u_s compressed:
  * four H applications and four additions.  H_t, H_mid, H_t1 are the operators at t,
  * t + dt/2 and t + dt (pass the same handle three times for a static H). */
 tdmps_status tdmps_rk4_step(tdmps_mpo H_t, tdmps_mpo H_mid, tdmps_mpo H_t1, tdmps_mps psi, double dt,
@@ -233,7 +233,7 @@ tdmps_status tdmps_heff_destroy(tdmps_heff op);
  * Field-driven dynamics: H(t) = H0 + E(t) M with E(t) = amplitude * sin(omega t) *
  * exp(-(t - t_center)^2 / (2 width^2)); the field enters through the one-body integrals of
  * Eq. (hamil), h(t) = h0 + E(t) m.  tdmps_pulse_forward propagates psi0 by nsteps RK4 steps
- * (Eqs. (k1-k4), (rk_add); stage times t, t+dt/2, t+dt/2, t+dt) and returns
+ * (the RK4 stage definitions and Eq. (rk_add); stage times t, t+dt/2, t+dt/2, t+dt) and returns
  * D = <psi_N|mu|psi_N> / <psi_N|psi_N>, keeping psi every checkpoint_every steps in the
  * trajectory handle.  tdmps_pulse_backward returns dD/d(amplitude) by the adjoint of the
  * discrete RK4 map: the states between checkpoints are recomputed and the adjoint stages

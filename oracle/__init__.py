@@ -11,8 +11,9 @@ that it follows):
                 of Eq. (hamil) built by applying second-quantised operators with
                 Jordan-Wigner signs; observables.
   slater     -- Slater-Condon matrix elements between determinants (independent of fci).
-  propagate  -- exact exp(-iHt) of Eq. (time_evo_opera), the RK4 map of Eqs. (k1-k4,
-                rk_add) and the Krylov map of Eqs. (kry_non, kry_orth, krylov_evo).
+  propagate  -- exact exp(-iHt) of Eq. (time_evo_opera), the RK4 map (the RK4 stage
+                definitions and Eq. (rk_add)) and the Krylov map of Eqs. (kry_non, kry_orth,
+                krylov_evo).
   mps        -- dense MPS with (N_up, N_dn) bond labels, Eq. (mps); sequential-SVD
                 decomposition; truncation to the D largest singular values; the
                 variational two-site fit of Eq. (add_min) computed by projection; RK4 and

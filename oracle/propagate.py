@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
 Units: atomic units, hbar = 1 (so the paper's 1.21 as step is dt = 0.05).
   * exact:   psi(t) = exp(-i H t) psi(0)                           Eq. (time_evo_opera)
-  * rk4:     k_s = -i dt H u_s, psi' = psi + (k1 + 2 k2 + 2 k3 + k4)/6  Eqs. (k1-k4, rk_add)
+  * rk4:     k_s = -i dt H u_s, psi' = psi + (k1 + 2 k2 + 2 k3 + k4)/6  the RK4 stage definitions and Eq. (rk_add)
              (the factor -i/hbar that the printed stage definitions drop is restored; the
              text states the map equals the 4th-order Taylor expansion of the propagator)
   * krylov:  basis phi^0 = psi, phi^{k+1} from H phi^k, either plainly normalised
@@ -98,7 +98,7 @@ def rk4_norm_eigenstate(E, dt):
 # H(t) = H0 + E(t) M with E(t) = A f(t), f(t) = sin(omega t) exp(-(t - tc)^2 / (2 tau^2)): the
 # time-dependent Hamiltonian of the dipole coupling to a laser pulse (Methods: the one-body
 # integrals of Eq. (hamil) carry the field).  Observable: D = <psi_N|mu|psi_N> / <psi_N|psi_N>
-# after N RK4 steps of Eqs. (k1-k4, rk_add) with stage times t, t+dt/2, t+dt/2, t+dt.
+# after N RK4 steps of the RK4 stage definitions and Eq. (rk_add) with stage times t, t+dt/2, t+dt/2, t+dt.
 
 def pulse_shape(omega, tc, tau):
     """f(t) such that E(t) = A f(t)."""

@@ -1,4 +1,4 @@
-// Time steps built from the fit: RK4 (Eqs. (k1-k4), (rk_add)) and Krylov (Eqs. (kry_non),
+// Time steps built from the fit: RK4 (the RK4 stage definitions and Eq. (rk_add)) and Krylov (Eqs. (kry_non),
 // (kry_orth), (krylov_evo)).  The m x m Krylov algebra runs on the host in FP64.
 #include <cmath>
 #include <cstdio>

@@ -3,7 +3,7 @@
 //
 // H(t) = H0 + E(t) M with E(t) = A sin(omega t) exp(-(t - tc)^2 / (2 tau^2)): the field enters
 // through the one-body integrals of Eq. (hamil), h(t) = h0 + E(t) m.  Observable after N steps
-// (Eqs. (k1-k4), (rk_add)): D = <psi_N|mu|psi_N> / <psi_N|psi_N>.
+// (the RK4 stage definitions and Eq. (rk_add)): D = <psi_N|mu|psi_N> / <psi_N|psi_N>.
 //
 // Every step is linear, psi_{n+1} = P_n psi_n, so dD/dA = sum_n 2 Re <lam_{n+1}| dP_n/dA psi_n>
 // with lam_N = (mu - D) psi_N / |psi_N|^2 and lam_n = P_n^H lam_{n+1}.  Reverse mode through
