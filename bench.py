@@ -76,7 +76,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp64", choices=list(PREC))
-    ap.add_argument("--krylov", type=int, default=0, help="Krylov steps to time (one sweep per fit)")
+    ap.add_argument("--krylov", type=int, default=1, help="Krylov steps to time (one sweep per fit)")
+    ap.add_argument("--mixed", type=int, default=1, help="also time the FP32 and BF16-split H_eff (FP64 runs only)")
     ap.add_argument("--krylov-m", type=int, default=12, help="Krylov dimension (12 in the benchmark definition)")
     ap.add_argument("--check", type=int, default=8, help="sampled outputs checked against Slater-Condon")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -176,6 +177,24 @@ def main():
     achieved = flops / (ms_kernel * 1e-3) / 1e12
 
     out = tout.cpu().numpy().view(np.complex128)
+    mixed = None
+    if args.mixed and args.precision == "fp64":
+        mixed = {}
+        for pname in ("fp32", "bf16x3"):
+            op.set_precision(PREC[pname])
+            if args.tune:
+                ctx.autotune(PREC[pname])
+            for _ in range(max(1, args.warmup)):
+                op.apply(tin.data_ptr(), tout.data_ptr())
+            pms, pk = timed(probe)
+            low = tout.cpu().numpy().view(np.complex128)
+            mixed[pname] = {"ms_per_apply": pms, "tflops_algorithmic": flops / (pms * 1e-3) / 1e12,
+                            "roofline_frac": flops / (float(np.mean(pk)) * 1e-3) / 1e12 / PEAK[pname],
+                            "max_abs_err_rel_to_max_fp64": float(np.abs(low - out).max() / np.abs(out).max()),
+                            "rel_l2_err_vs_fp64": float(np.linalg.norm(low - out) / np.linalg.norm(out)),
+                            "speedup_vs_fp64": ms_step / pms}
+            progress(f"{pname}: {pms:.2f} ms per apply")
+        op.set_precision(PREC[args.precision])
     # batching baseline: the same H_eff*theta with one kernel launch per block product
     batching = {"graph_ms": graph_ms, "grouped_eager_ms": grouped_ms, "graph_autotuned_ms": tuned_ms,
                 "tile_rule_timed": tile_rule, "autotune_seconds": t_tune,
@@ -267,6 +286,7 @@ def main():
         "cpu_baseline": cpu,
         "krylov": krylov,
         "batching": batching,
+        "mixed_precision": mixed,
         "check": check,
         "plan": {"executed_flops_T_stage": plan_stats[1], "executed_flops_final_stage": plan_stats[2],
                  "T_bytes": plan_stats[3], "tasks": [int(plan_stats[4]), int(plan_stats[5])],

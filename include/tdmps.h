@@ -225,6 +225,9 @@ tdmps_status tdmps_heff_layout(tdmps_heff op, int32_t which, int64_t* total_doub
                                int32_t* blocks);
 /* theta_out = H_eff theta_in; both device pointers (FP64 interleaved complex). */
 tdmps_status tdmps_heff_apply(tdmps_heff op, const void* theta_in_dev, void* theta_out_dev);
+/* Contraction precision of later applies (TDMPS_FP64, TDMPS_FP32, TDMPS_BF16X3); the
+ * environments are kept.  TDMPS_ERR_ARG for other values. */
+tdmps_status tdmps_heff_set_precision(tdmps_heff op, int32_t precision);
 /* Algorithmic flops of one apply (8 per complex multiply-add of the block products). */
 tdmps_status tdmps_heff_flops(tdmps_heff op, double* flops);
 tdmps_status tdmps_heff_destroy(tdmps_heff op);

@@ -572,6 +572,21 @@ extern "C" tdmps_status tdmps_heff_apply(tdmps_heff h, const void* in, void* out
   });
 }
 
+extern "C" tdmps_status tdmps_heff_set_precision(tdmps_heff h, int32_t precision) {
+  return guard([&] {
+    TDMPS_REQUIRE(h, TDMPS_ERR_ARG, "NULL argument");
+    TDMPS_REQUIRE(precision == TDMPS_FP64 || precision == TDMPS_FP32 || precision == TDMPS_BF16X3, TDMPS_ERR_ARG,
+                  "unknown precision");
+    if (precision == h->precision) return;
+    dev_bind(h->ctx->device, h->ctx->stream);
+    dev_sync(h->ctx->stream);
+    graph_destroy(h->graph);
+    h->graph = nullptr;
+    h->plan.reset();
+    h->precision = precision;
+  });
+}
+
 extern "C" tdmps_status tdmps_heff_flops(tdmps_heff h, double* flops) {
   return guard([&] {
     TDMPS_REQUIRE(h && flops, TDMPS_ERR_ARG, "NULL argument");

@@ -5,10 +5,12 @@
 // stream runs after every earlier use of the block.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
 #include <unordered_map>
+#include <vector>
 
 #include "common.h"
 #include "kernels.h"
@@ -105,9 +107,62 @@ void dev_free(void* p) {
   g_free[it->second.key].emplace(it->second.size, p);
 }
 
+// Uploads go through pinned staging blocks so that they are truly asynchronous: a copy from
+// pageable memory makes the host wait for the stream, which serialised host planning with
+// device work.  A staging block is reused once the event recorded behind its last copy has
+// completed; per (device, stream) at most PIN_CAP bytes are staged, beyond which the host
+// waits for the oldest copy.
+namespace {
+struct PinBlock {
+  char* p;
+  size_t size;
+  hipEvent_t ev;
+  uint64_t stamp;  // order of last use
+};
+std::mutex g_pin_mu;
+std::map<Key, std::vector<PinBlock>> g_pin;
+uint64_t g_pin_clock = 0;
+constexpr size_t PIN_MIN = (size_t)64 << 10, PIN_CAP = (size_t)1 << 30;
+}  // namespace
+
 void dev_h2d(void* dst, const void* src, size_t bytes, void* stream) {
   if (!bytes) return;
-  check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, (hipStream_t)stream), "hipMemcpyAsync H2D");
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  int device = 0;
+  check(hipGetDevice(&device), "hipGetDevice");
+  auto& blocks = g_pin[Key{device, stream}];
+  PinBlock* use = nullptr;
+  size_t total = 0;
+  for (auto& b : blocks) {
+    total += b.size;
+    if (b.size < bytes || (use && use->size <= b.size)) continue;
+    if (hipEventQuery(b.ev) == hipSuccess) use = &b;
+  }
+  if (!use) {
+    if (total + bytes > PIN_CAP && !blocks.empty()) {
+      // wait for the least recently used block that is large enough, else grow anyway
+      PinBlock* old = nullptr;
+      for (auto& b : blocks)
+        if (b.size >= bytes && (!old || b.stamp < old->stamp)) old = &b;
+      if (old) {
+        check(hipEventSynchronize(old->ev), "hipEventSynchronize");
+        use = old;
+      }
+    }
+    if (!use) {
+      size_t sz = PIN_MIN;
+      while (sz < bytes) sz <<= 1;
+      PinBlock b{nullptr, sz, nullptr, 0};
+      check(hipHostMalloc((void**)&b.p, sz, hipHostMallocDefault), "hipHostMalloc");
+      check(hipEventCreateWithFlags(&b.ev, hipEventDisableTiming), "hipEventCreate");
+      blocks.push_back(b);
+      use = &blocks.back();
+    }
+  }
+  std::memcpy(use->p, src, bytes);
+  check(hipMemcpyAsync(dst, use->p, bytes, hipMemcpyHostToDevice, (hipStream_t)stream), "hipMemcpyAsync H2D");
+  check(hipEventRecord(use->ev, (hipStream_t)stream), "hipEventRecord");
+  use->stamp = ++g_pin_clock;
 }
 
 void dev_d2h(void* dst, const void* src, size_t bytes, void* stream) {

@@ -224,7 +224,12 @@ struct GemmPlan {
                int ldb, int opB, int k, int nred, cplx alpha);
   // device copies of the task lists (finalize) and asynchronous launch
   static constexpr int NCFG = GEMM_NCFG;
-  DevBuf dsegs, dtasks[NCFG], dtile[NCFG], wspace, dred;
+  // all task tables of the plan in one device buffer (one upload)
+  DevBuf dtab, wspace;
+  const GemmSeg* dsegs = nullptr;
+  const GemmTask* dtasks[NCFG] = {};
+  const int32_t* dtile[NCFG] = {};
+  const ReduceTask* dred = nullptr;
   std::vector<int64_t> htile_base[NCFG];  // first tile of every task (per-task launches)
   std::vector<int64_t> red_base;
   int nred_tasks = 0;

@@ -224,13 +224,7 @@ void GemmPlan::finalize(Ctx* ctx, int precision) {
     wspace = DevBuf(ws * sizeof(cplx));
     for (auto& po : part_of) out[po.first].C = wspace.c() + po.second;
     for (size_t k = 0; k < red.size(); ++k) red[k].parts = wspace.c() + red_base[k];
-    dred = DevBuf(red.size() * sizeof(ReduceTask));
-    dev_h2d(dred.p, red.data(), red.size() * sizeof(ReduceTask), ctx->stream);
     nred_tasks = (int)red.size();
-  }
-  if (!nsegs.empty()) {
-    dsegs = DevBuf(nsegs.size() * sizeof(GemmSeg));
-    dev_h2d(dsegs.p, nsegs.data(), nsegs.size() * sizeof(GemmSeg), ctx->stream);
   }
   // Tile shape per task: a forced shape (tdmps_ctx_set_tile_config), else the measured best
   // shape of the task's bucket (tdmps_ctx_autotune), else the least padded MFMA work divided
@@ -261,10 +255,13 @@ void GemmPlan::finalize(Ctx* ctx, int precision) {
   };
   std::vector<int> choice(out.size());
   for (size_t i = 0; i < out.size(); ++i) choice[i] = pick(out[i]);
+  // Host image of the device tables: segments, reduction tasks, then per tile shape the task
+  // list and the tile -> task map, each 256-byte aligned; one upload.
+  std::vector<std::vector<GemmTask>> sel(NCFG);
+  std::vector<std::vector<int32_t>> tmap(NCFG);
   for (int cfg = 0; cfg < NCFG; ++cfg) {
-    std::vector<GemmTask> sel;
     int64_t base = 0;
-    int tm = gemm_tile_m(cfg), tn = gemm_tile_n(cfg);
+    const int tm = gemm_tile_m(cfg), tn = gemm_tile_n(cfg);
     for (size_t i = 0; i < out.size(); ++i) {
       if (choice[i] != cfg) continue;
       GemmTask t = out[i];
@@ -272,22 +269,47 @@ void GemmPlan::finalize(Ctx* ctx, int precision) {
       t.tiles_n = (t.n + tn - 1) / tn;
       t.tile_base = base;
       base += (int64_t)t.nbatch * t.tiles_m * t.tiles_n;
-      sel.push_back(t);
+      sel[cfg].push_back(t);
     }
-    ntask[cfg] = (int)sel.size();
+    ntask[cfg] = (int)sel[cfg].size();
     ntiles[cfg] = base;
     htile_base[cfg].clear();
-    for (auto& t : sel) htile_base[cfg].push_back(t.tile_base);
-    if (sel.empty()) continue;
-    dtasks[cfg] = DevBuf(sel.size() * sizeof(GemmTask));
-    dev_h2d(dtasks[cfg].p, sel.data(), sel.size() * sizeof(GemmTask), ctx->stream);
-    std::vector<int32_t> tt((size_t)base);
-    for (size_t k = 0; k < sel.size(); ++k) {
-      int64_t nt = (int64_t)sel[k].nbatch * sel[k].tiles_m * sel[k].tiles_n;
-      std::fill(tt.begin() + sel[k].tile_base, tt.begin() + sel[k].tile_base + nt, (int32_t)k);
+    for (auto& t : sel[cfg]) htile_base[cfg].push_back(t.tile_base);
+    tmap[cfg].resize((size_t)base);
+    for (size_t k = 0; k < sel[cfg].size(); ++k) {
+      const int64_t nt = (int64_t)sel[cfg][k].nbatch * sel[cfg][k].tiles_m * sel[cfg][k].tiles_n;
+      std::fill(tmap[cfg].begin() + sel[cfg][k].tile_base, tmap[cfg].begin() + sel[cfg][k].tile_base + nt,
+                (int32_t)k);
     }
-    dtile[cfg] = DevBuf(tt.size() * sizeof(int32_t));
-    dev_h2d(dtile[cfg].p, tt.data(), tt.size() * sizeof(int32_t), ctx->stream);
+  }
+  auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  size_t bytes = 0;
+  const size_t o_segs = bytes;
+  bytes = align(bytes + nsegs.size() * sizeof(GemmSeg));
+  const size_t o_red = bytes;
+  bytes = align(bytes + red.size() * sizeof(ReduceTask));
+  size_t o_task[NCFG], o_tile[NCFG];
+  for (int cfg = 0; cfg < NCFG; ++cfg) {
+    o_task[cfg] = bytes;
+    bytes = align(bytes + sel[cfg].size() * sizeof(GemmTask));
+    o_tile[cfg] = bytes;
+    bytes = align(bytes + tmap[cfg].size() * sizeof(int32_t));
+  }
+  std::vector<char> img(bytes);
+  if (!nsegs.empty()) std::memcpy(img.data() + o_segs, nsegs.data(), nsegs.size() * sizeof(GemmSeg));
+  if (!red.empty()) std::memcpy(img.data() + o_red, red.data(), red.size() * sizeof(ReduceTask));
+  for (int cfg = 0; cfg < NCFG; ++cfg) {
+    if (!sel[cfg].empty()) std::memcpy(img.data() + o_task[cfg], sel[cfg].data(), sel[cfg].size() * sizeof(GemmTask));
+    if (!tmap[cfg].empty()) std::memcpy(img.data() + o_tile[cfg], tmap[cfg].data(), tmap[cfg].size() * sizeof(int32_t));
+  }
+  dtab = DevBuf(bytes);
+  dev_h2d(dtab.p, img.data(), bytes, ctx->stream);
+  char* b = (char*)dtab.p;
+  dsegs = (const GemmSeg*)(b + o_segs);
+  dred = red.empty() ? nullptr : (const ReduceTask*)(b + o_red);
+  for (int cfg = 0; cfg < NCFG; ++cfg) {
+    dtasks[cfg] = (const GemmTask*)(b + o_task[cfg]);
+    dtile[cfg] = (const int32_t*)(b + o_tile[cfg]);
   }
 }
 
@@ -295,19 +317,19 @@ void GemmPlan::launch(Ctx* ctx, int precision, bool batched) {
   for (int cfg = 0; cfg < NCFG; ++cfg) {
     if (ntask[cfg] <= 0) continue;
     if (batched) {
-      launch_gemm((const GemmTask*)dtasks[cfg].p, (const GemmSeg*)dsegs.p, (const int32_t*)dtile[cfg].p, ntiles[cfg],
+      launch_gemm(dtasks[cfg], dsegs, dtile[cfg], ntiles[cfg],
                   cfg, precision, ctx->stream, 0);
     } else {
       // one launch per task: the grid covers the task's own tiles only
       for (size_t t = 0; t < htile_base[cfg].size(); ++t) {
         const int64_t b0 = htile_base[cfg][t];
         const int64_t b1 = t + 1 < htile_base[cfg].size() ? htile_base[cfg][t + 1] : ntiles[cfg];
-        launch_gemm((const GemmTask*)dtasks[cfg].p, (const GemmSeg*)dsegs.p, (const int32_t*)dtile[cfg].p, b1 - b0,
+        launch_gemm(dtasks[cfg], dsegs, dtile[cfg], b1 - b0,
                     cfg, precision, ctx->stream, b0);
       }
     }
   }
-  if (nred_tasks > 0) launch_reduce((const ReduceTask*)dred.p, nred_tasks, ctx->stream);
+  if (nred_tasks > 0) launch_reduce(dred, nred_tasks, ctx->stream);
 }
 
 void GemmPlan::run(Ctx* ctx, int precision, bool batched) {

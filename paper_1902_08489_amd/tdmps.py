@@ -96,6 +96,7 @@ _SIGS = {
     "tdmps_heff_create": (ct.c_int32, [_P, _P, _P, ct.c_int32, ct.c_int32, _PP]),
     "tdmps_heff_layout": (ct.c_int32, [_P, ct.c_int32, _I64, _I64, _I32]),
     "tdmps_heff_apply": (ct.c_int32, [_P, _P, _P]),
+    "tdmps_heff_set_precision": (ct.c_int32, [_P, ct.c_int32]),
     "tdmps_heff_flops": (ct.c_int32, [_P, _D]),
     "tdmps_heff_destroy": (ct.c_int32, [_P]),
     "tdmps_pulse_forward": (ct.c_int32, [_P, _D, _D, _P, _P, ct.POINTER(Pulse), ct.c_double, ct.c_int32, ct.c_int32,
@@ -393,6 +394,9 @@ class Heff:
 
     def apply(self, in_ptr, out_ptr):
         _check(_LIB.tdmps_heff_apply(self.h, ct.c_void_p(in_ptr), ct.c_void_p(out_ptr)))
+
+    def set_precision(self, precision):
+        _check(_LIB.tdmps_heff_set_precision(self.h, int(precision)))
 
     def flops(self):
         f = ct.c_double()
