@@ -59,6 +59,7 @@ void publish(Ctx* ctx, const Contractor& C) {
   ctx->counters[14] = C.n_sandwich;
   ctx->counters[15] = C.t_qr;
   ctx->counters[16] = C.t_plan;
+  dev_alloc_stats(&ctx->counters[17], &ctx->counters[18]);
 }
 
 void check_prm(const tdmps_fit_params* p) {

@@ -5,6 +5,7 @@
 // stream runs after every earlier use of the block.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -75,6 +76,15 @@ void dev_bind(int device, void* stream) {
   dev_set_device(device);
 }
 
+static int64_t g_nmalloc = 0;
+static double g_tmalloc = 0;
+
+void dev_alloc_stats(double* count, double* seconds) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  *count = (double)g_nmalloc;
+  *seconds = g_tmalloc;
+}
+
 void* dev_alloc(size_t bytes) {
   size_t b = round_size(bytes);
   std::lock_guard<std::mutex> lk(g_mu);
@@ -86,7 +96,11 @@ void* dev_alloc(size_t bytes) {
     return p;
   }
   void* p = nullptr;
-  if (hipMalloc(&p, b) != hipSuccess) {
+  const auto t0 = std::chrono::steady_clock::now();
+  ++g_nmalloc;
+  const hipError_t e = hipMalloc(&p, b);
+  g_tmalloc += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (e != hipSuccess) {
     (void)hipGetLastError();
     release_cache();
     p = nullptr;
@@ -165,10 +179,41 @@ void dev_h2d(void* dst, const void* src, size_t bytes, void* stream) {
   use->stamp = ++g_pin_clock;
 }
 
+// Readbacks land in a pinned bounce buffer per (device, stream): a copy into pageable memory
+// is staged by the runtime and costs far more latency than the copy itself, and the host
+// waits for every readback (singular values, convergence counters, scalar results).
+namespace {
+std::map<Key, std::pair<char*, size_t>> g_bounce;
+constexpr size_t BOUNCE_MAX = (size_t)64 << 20;
+}  // namespace
+
 void dev_d2h(void* dst, const void* src, size_t bytes, void* stream) {
   if (!bytes) return;
-  check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, (hipStream_t)stream), "hipMemcpyAsync D2H");
+  if (bytes > BOUNCE_MAX) {
+    check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, (hipStream_t)stream), "hipMemcpyAsync D2H");
+    check(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+    return;
+  }
+  char* buf = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    int device = 0;
+    check(hipGetDevice(&device), "hipGetDevice");
+    auto& b = g_bounce[Key{device, stream}];
+    if (b.second < bytes) {
+      if (b.first) check(hipHostFree(b.first), "hipHostFree");
+      b.first = nullptr;
+      b.second = 0;
+      size_t sz = (size_t)64 << 10;
+      while (sz < bytes) sz <<= 1;
+      check(hipHostMalloc((void**)&b.first, sz, hipHostMallocDefault), "hipHostMalloc");
+      b.second = sz;
+    }
+    buf = b.first;
+  }
+  check(hipMemcpyAsync(buf, src, bytes, hipMemcpyDeviceToHost, (hipStream_t)stream), "hipMemcpyAsync D2H");
   check(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+  std::memcpy(dst, buf, bytes);
 }
 
 void dev_d2d(void* dst, const void* src, size_t bytes, void* stream) {

@@ -90,6 +90,7 @@ void dev_set_device(int device);
 void dev_bind(int device, void* stream);
 void* dev_alloc(size_t bytes);  // returns nullptr when out of memory
 void dev_free(void* p);
+void dev_alloc_stats(double* count, double* seconds);  // hipMalloc calls and seconds so far (process)
 void dev_h2d(void* dst, const void* src, size_t bytes, void* stream);
 void dev_d2h(void* dst, const void* src, size_t bytes, void* stream);  // host data valid on return
 void dev_d2d(void* dst, const void* src, size_t bytes, void* stream);
@@ -121,9 +122,11 @@ void launch_copy(const CopyTask* tasks, int ntasks, void* stream);
 void launch_svd_init(const SvdMat* mats, int nmats, void* stream);  // V = identity
 // One round (block pairs of the circle schedule, round >= 0; or the diagonal round of a sweep,
 // round < 0) for all matrices; total_pairs = sum nblk/2; rot_counter is incremented once per
-// workgroup that rotated.  A sweep is the diagonal round followed by rounds 0 .. nblk-2.
+// workgroup that rotated.  A sweep is the diagonal round followed by rounds 0 .. nblk-2.  If
+// prev_counter is given and holds 0 (the previous sweep rotated nothing: converged), the
+// round does nothing, so sweeps can be queued ahead of the convergence test.
 void launch_svd_round(const SvdMat* mats, int nmats, int64_t total_pairs, int round, double tol, int32_t* rot_counter,
-                      void* stream);
+                      const int32_t* prev_counter, void* stream);
 void launch_svd_norms(const SvdMat* mats, int nmats, int max_k, double* sigma_out, void* stream);
 void launch_scale(cplx* x, int64_t n, cplx alpha, void* stream);
 // QR preconditioning of the Jacobi SVD: factor panel j0 (one workgroup per matrix); apply

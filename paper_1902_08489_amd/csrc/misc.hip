@@ -159,7 +159,8 @@ __device__ __forceinline__ void wave_sync() {
 
 __global__ __launch_bounds__(64 * SVD_WAVES) void svd_block_round_kernel(const SvdMat* __restrict__ mats, int nmats,
                                                                          int round, double tol,
-                                                                         int32_t* __restrict__ counter) {
+                                                                         int32_t* __restrict__ counter,
+                                                                         const int32_t* __restrict__ prev) {
   static_assert(SVD_PW == 16, "one 16 x 16 MFMA tile per block pair");
   typedef double v4d __attribute__((ext_vector_type(4)));
   __shared__ double2 Mp[SVD_WAVES][SVD_PW][SVD_PW + 1];  // per-wave partial Gram matrices
@@ -167,6 +168,7 @@ __global__ __launch_bounds__(64 * SVD_WAVES) void svd_block_round_kernel(const S
   __shared__ double2 Qs[SVD_PW][SVD_PW + 1];
   __shared__ int col[SVD_PW];
   __shared__ int rotated;
+  if (prev != nullptr && *prev == 0) return;  // converged in an earlier sweep (uniform)
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
   const int j = find_mat(mats, nmats, blockIdx.x);
@@ -355,10 +357,10 @@ void launch_svd_init(const SvdMat* mats, int nmats, void* stream) {
 }
 
 void launch_svd_round(const SvdMat* mats, int nmats, int64_t total_pairs, int round, double tol, int32_t* counter,
-                      void* stream) {
+                      const int32_t* prev, void* stream) {
   if (nmats <= 0 || total_pairs <= 0) return;
   hipLaunchKernelGGL(svd_block_round_kernel, dim3((unsigned)total_pairs), dim3(64 * SVD_WAVES), 0, (hipStream_t)stream, mats,
-                     nmats, round, tol, counter);
+                     nmats, round, tol, counter, prev);
   check(hipGetLastError(), "svd round launch");
 }
 

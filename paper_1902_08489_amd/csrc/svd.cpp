@@ -150,18 +150,27 @@ struct SvdBatch {
     t_qr = wall_seconds() - tq;
     const SvdMat* dm = st.put(ctx, xm);
     launch_svd_init(dm, nm, ctx->stream);
-    DevBuf counter(sizeof(int32_t));
+    // Sweeps are queued in batches with one rotation counter each; a sweep whose predecessor
+    // rotated nothing skips on the device, so the host reads the counters once per batch.
     const double tol = 1e-15;
     const int max_sweeps = 60;
+    DevBuf counter(max_sweeps * sizeof(int32_t));
+    int32_t* dc = (int32_t*)counter.p;
+    dev_zero(counter.p, counter.bytes, ctx->stream);
     bool converged = maxn <= 1;
-    int sweeps_done = 0;
-    for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep, ++sweeps_done) {
-      dev_zero(counter.p, sizeof(int32_t), ctx->stream);
-      for (int r = -1; r < maxrounds; ++r)
-        launch_svd_round(dm, nm, pairs, r, tol, (int32_t*)counter.p, ctx->stream);
-      int32_t rot = 0;
-      dev_d2h(&rot, counter.p, sizeof(int32_t), ctx->stream);
-      converged = rot == 0;
+    int sweeps_done = 0, queued = 0;
+    std::vector<int32_t> rot(max_sweeps);
+    while (!converged && queued < max_sweeps) {
+      const int batch = std::min(max_sweeps - queued, queued == 0 ? 6 : 3);
+      for (int sw = queued; sw < queued + batch; ++sw)
+        for (int r = -1; r < maxrounds; ++r)
+          launch_svd_round(dm, nm, pairs, r, tol, dc + sw, sw > 0 ? dc + sw - 1 : nullptr, ctx->stream);
+      dev_d2h(rot.data() + queued, dc + queued, batch * sizeof(int32_t), ctx->stream);
+      for (int sw = queued; sw < queued + batch && !converged; ++sw) {
+        sweeps_done = sw + 1;
+        converged = rot[sw] == 0;
+      }
+      queued += batch;
     }
     TDMPS_REQUIRE(converged, TDMPS_ERR_NUMERIC, "Jacobi SVD did not converge");
     sweeps = sweeps_done;
