@@ -56,6 +56,32 @@ def test_gradient_matches_oracle(case, nsteps, every):
     assert abs(g - gr) < RTOL * max(abs(gr), 1e-3 * abs(D))
 
 
+def test_gradient_matches_oracle_L8_full_bond_dimension(ctx):
+    """L = 8, N = 7 (FCI dimension 3920) with D = 256 >= D_FCI = 160 and four sweeps per fit
+    (two leave the fits from the determinant start unconverged at the 1e-10 level): every fit
+    is exact, so the library's value and adjoint equal the dense discrete map's to 1e-10."""
+    L = 8
+    h, eri, _ = synth.integrals(L)
+    m = synth.dipole_matrix(L)
+    occ = synth.ionized_determinant(L, 8)
+    space = fci.Space.sector(L, *synth.occ_charge(occ))
+    H0 = fci.hamiltonian(space, h, eri)
+    M = fci.one_body_operator(space, m)
+    psi0 = space.restrict(om.to_full(om.from_occ(occ)))
+    p = dict(omega=2.0, t_center=0.1, width=0.08)
+    A, dt, nsteps, every = 0.6, 0.02, 10, 4
+    prm = T.fit_params(Dmax=256, n_sweeps=4)
+    traj = T.Trajectory(T.MPO.from_integrals(ctx, h, eri, 0.0), h, m, T.MPO.one_body(ctx, m),
+                        T.MPS.from_determinant(ctx, occ), A, p["omega"], p["t_center"], p["width"], dt, nsteps,
+                        every, prm)
+    g = traj.backward()
+    f = propagate.pulse_shape(p["omega"], p["t_center"], p["width"])
+    D, gr = propagate.dipole_response_gradient(H0, M, M, psi0, f, A, dt, nsteps)
+    print(f"L=8: D {traj.value:.12f} oracle {D:.12f}; dD/dA {g:.12e} oracle {gr:.12e}")
+    assert abs(traj.value - D) < 1e-10 * abs(D)
+    assert abs(g - gr) < 1e-10 * abs(gr)
+
+
 def test_autograd_and_finite_difference(case):
     import torch
     from paper_1902_08489_amd.autograd import dipole_after_pulse
