@@ -202,7 +202,10 @@ tdmps_status tdmps_mps_compress(int32_t nterms, const double* beta, const tdmps_
  * psi/|psi|; each next one fitted from H phi^k (minus the projections on all previous
  * vectors for TDMPS_KRYLOV_ORTHO) and normalised; N and H from overlaps and sandwiches;
  * out ~ |psi| sum_k [exp(-i dt N^-1 H)]_{k0} phi^k.  Nmat/Hmat (m*m interleaved complex,
- * row-major) may be NULL.  Returns TDMPS_ERR_SINGULAR if N is not positive definite. */
+ * row-major) may be NULL.  With TDMPS_KRYLOV_ORTHO the basis stops early when the space is
+ * invariant (the part of H phi^k orthogonal to the basis below 1e-10 of H phi^k, e.g. psi an
+ * eigenstate): the step then uses the vectors found so far and the unused rows and columns
+ * of Nmat/Hmat are 0.  Returns TDMPS_ERR_SINGULAR if N is not positive definite. */
 tdmps_status tdmps_krylov_step(tdmps_mpo H, tdmps_mps psi, double dt, int32_t m, int32_t flags,
                                const tdmps_fit_params* prm, tdmps_mps* out, double* Nmat, double* Hmat);
 /* RK4 step (the RK4 stage definitions and Eq. (rk_add)) with k_s = -i dt H(t_s) u_s fitted, u_s compressed:

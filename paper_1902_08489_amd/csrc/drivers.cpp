@@ -185,12 +185,18 @@ Mps* krylov_step(Contractor& C, const MpoHost* H, const Mps* psi, double dt, int
     for (int j = 0; j < n; ++j) b.push_back(phi[j].get());
     return b;
   };
+  // The orthogonal basis stops early if the space is invariant: when the component of
+  // H phi^k orthogonal to the basis is below 1e-10 of H phi^k (e.g. psi an eigenstate), the
+  // step uses the k + 1 vectors found so far (unused rows and columns of N and H stay 0).
+  int meff = m;
   for (int k = 0; k < m - 1; ++k) {
     // H_jk = <phi_j|H|phi_k> for all j <= k in one batched sweep
     const std::vector<cplx> hk = sandwich_many(C, *H, bras(k + 1), phi[k].get());
+    double proj = 0;
     for (int j = 0; j <= k; ++j) {
       Hm[j * m + k] = z(hk[j]);
       Hm[k * m + j] = std::conj(Hm[j * m + k]);
+      proj += std::norm(Hm[j * m + k]) / N[j * m + j].real();
     }
     std::vector<FitTerm> terms;
     if (orthogonal)
@@ -202,7 +208,12 @@ Mps* krylov_step(Contractor& C, const MpoHost* H, const Mps* psi, double dt, int
     if (progress)
       std::fprintf(stderr, "krylov: vector %d of %d after %.1f s\n", k + 1, m - 1, wall_seconds() - t_start);
     double nn = overlap(C, nxt.get(), nxt.get()).x;
-    TDMPS_REQUIRE(nn > 0 && std::isfinite(nn), TDMPS_ERR_SINGULAR, "Krylov vector vanished");
+    TDMPS_REQUIRE(nn >= 0 && std::isfinite(nn), TDMPS_ERR_NUMERIC, "Krylov vector is not finite");
+    if (orthogonal && nn <= 1e-20 * (proj + nn)) {
+      meff = k + 1;
+      break;
+    }
+    TDMPS_REQUIRE(nn > 0, TDMPS_ERR_SINGULAR, "Krylov vector vanished");
     scale_mps(C.ctx, nxt.get(), cplx{1.0 / std::sqrt(nn), 0.0});
     phi.push_back(std::move(nxt));
     const std::vector<cplx> nk = sandwich_many(C, I, bras(k + 2), phi[k + 1].get());
@@ -211,16 +222,22 @@ Mps* krylov_step(Contractor& C, const MpoHost* H, const Mps* psi, double dt, int
       N[(k + 1) * m + j] = std::conj(N[j * m + k + 1]);
     }
   }
-  {
+  if (meff == m) {
     const std::vector<cplx> hl = sandwich_many(C, *H, bras(m), phi[m - 1].get());
     for (int j = 0; j < m; ++j) {
       Hm[j * m + m - 1] = z(hl[j]);
       Hm[(m - 1) * m + j] = std::conj(Hm[j * m + m - 1]);
     }
   }
-  auto c = krylov_coefficients(m, N, Hm, dt, orthogonal);
+  std::vector<zd> Ns((size_t)meff * meff), Hs((size_t)meff * meff);
+  for (int r = 0; r < meff; ++r)
+    for (int q = 0; q < meff; ++q) {
+      Ns[r * meff + q] = N[r * m + q];
+      Hs[r * meff + q] = Hm[r * m + q];
+    }
+  auto c = krylov_coefficients(meff, Ns, Hs, dt, orthogonal);
   std::vector<FitTerm> terms;
-  for (int k = 0; k < m; ++k) terms.push_back({cplx{s0 * c[k].real(), s0 * c[k].imag()}, phi[k].get()});
+  for (int k = 0; k < meff; ++k) terms.push_back({cplx{s0 * c[k].real(), s0 * c[k].imag()}, phi[k].get()});
   Mps* out = fit(C, nullptr, cplx{1, 0}, nullptr, terms, prm, nullptr);
   if (Nout) *Nout = N;
   if (Hout) *Hout = Hm;

@@ -277,6 +277,49 @@ def test_error_paths_on_device(ctx, sys6):
     assert e.value.code == -1
 
 
+@pytest.mark.parametrize("code,e0", [(0, 0.7), (3, 0.0)])
+def test_one_dimensional_sectors(ctx, code, e0):
+    """The vacuum and the fully filled state span one-dimensional sectors, so H acts on them as
+    the scalar <det|H|det> + e0 (Slater-Condon): apply_H gives that multiple, and the
+    orthogonal Krylov basis is invariant after one vector, so the step is the exact phase
+    exp(-i E dt) (the basis stops early; unused entries of N, H are zero)."""
+    L = 6
+    h, eri, _ = synth.integrals(L)
+    mpo = T.MPO.from_integrals(ctx, h, eri, e0)
+    occ = np.full(L, code, np.uint8)
+    st = T.MPS.from_determinant(ctx, occ)
+    m = slater.occ_to_mask(tuple(int(x) for x in occ))
+    E = slater.SlaterCondon(h, eri).element(m, m) + e0
+    prm = T.fit_params(Dmax=8, n_sweeps=2)
+    out, _ = T.apply_H(mpo, 1.0, st, [], prm)
+    assert rel(dense(out), E * dense(st)) < 1e-12
+    k, N, Hm = T.krylov_step(mpo, st, 0.05, 4, True, prm)
+    assert rel(dense(k), np.exp(-1j * E * 0.05) * dense(st)) < 1e-12
+    assert abs(Hm[0, 0] - E) < 1e-12 * max(abs(E), 1) and np.all(N[1:, :] == 0) and np.all(Hm[:, 1:] == 0)
+    k2, _, _ = T.krylov_step(mpo, st, 0.05, 4, False, prm)
+    assert rel(dense(k2), np.exp(-1j * E * 0.05) * dense(st)) < 1e-10
+
+
+def test_degenerate_parameters(ctx, sys8):
+    """dt = 0 leaves the state unchanged; alpha = 0 gives the zero state (no division by a
+    vanishing norm); Dmax = 1 keeps one state per bond and matches the oracle's replica."""
+    psi = T.MPS.from_determinant(ctx, sys8.occ)
+    prm = T.fit_params(Dmax=64, n_sweeps=2)
+    out, _ = T.rk4_step(sys8.mpo, psi, 0.0, prm)
+    assert rel(dense(out), dense(psi)) < 1e-14
+    z, _ = T.apply_H(sys8.mpo, 0.0, psi, [], prm)
+    dz = dense(z)
+    assert np.all(np.isfinite(dz)) and np.linalg.norm(dz) == 0.0
+    Nu, Nd = sys8.Q
+    bonds, data = synth.random_state(8, Nu, Nd, 10, seed=5)
+    rs = T.MPS.from_blocks(ctx, bonds, data)
+    one, _ = T.apply_H(sys8.mpo, 1.0, rs, [], T.fit_params(Dmax=1, n_sweeps=2, svd_cutoff=TRUNC_CUT))
+    assert one.bond_dims().max() == 1
+    ops = om.DenseOps(sys8.Hf, Dmax=1, n_sweeps=2, cutoff=TRUNC_CUT)
+    ref = om.to_full(ops.apply_H(1.0, blocks_to_oracle(bonds, data), []))
+    assert rel(dense(one), ref) < RTOL
+
+
 def test_deterministic_repeat(ctx, sys8):
     psi = T.MPS.from_determinant(ctx, sys8.occ)
     prm = T.fit_params(Dmax=32, n_sweeps=2)
