@@ -18,6 +18,8 @@ Other workloads of the benchmark set (each prints its own JSON line; not the def
                         dipole against the FP64 run (default L = 30, D = 1024)
   --workload gradient   field-driven RK4 forward + adjoint backward for dD/dA
                         (default L = 16, D = 256, 200 steps of 0.02, checkpoints every 20)
+  --workload rdm        one-particle reduced density matrix of a state in one sweep
+                        (default L = 16, D = 256)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32|bf16x3]
        [--krylov 0|1] [--no-cpu-baseline] [--check N] [--workload heff|krylov|precision|gradient]
@@ -87,7 +89,7 @@ def main():
                     help="copy 1 GiB device to device once before timing (reference for HBM byte counters)")
     ap.add_argument("--L", type=int, default=None)
     ap.add_argument("--D", type=int, default=None)
-    ap.add_argument("--workload", default="heff", choices=["heff", "krylov", "precision", "gradient"])
+    ap.add_argument("--workload", default="heff", choices=["heff", "krylov", "precision", "gradient", "rdm"])
     ap.add_argument("--dt", type=float, default=None)
     ap.add_argument("--sweeps", type=int, default=1, help="fit sweeps per H application (Krylov workloads)")
     ap.add_argument("--rk4-steps", type=int, default=200)
@@ -304,6 +306,26 @@ def other_workload(args, progress):
     ctx = T.Context(0, stream=side.cuda_stream)
     line = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "data": "synthetic (seeded integrals and block-sparse state)"}
+    if args.workload == "rdm":
+        L = args.L or 16
+        D = args.D or 256
+        N0 = L
+        Nu, Nd = (N0 - 1) // 2, N0 - 1 - (N0 - 1) // 2
+        bk, dk = synth.random_state(L, Nu, Nd, D, sigma=1.0, seed=L + 5)
+        psi = T.MPS.from_blocks(ctx, bk, dk)
+        for _ in range(args.warmup):
+            T.one_rdm(psi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g = T.one_rdm(psi)
+        dt = (time.perf_counter() - t0) / args.steps
+        line.update({"metric": f"1-RDM evaluations/s @L={L} D={D}", "value": 1.0 / dt, "unit": "1/s",
+                     "ms_per_step": dt * 1e3, "dtype": "fp64",
+                     "config": {"workload": f"gamma_pq of a random block state, L={L} N={N0 - 1} D={D}"},
+                     "trace": float(np.trace(g).real), "hermiticity": float(np.abs(g - g.conj().T).max())})
+        print(json.dumps(line), flush=True)
+        return
     if args.workload in ("krylov", "precision"):
         L = args.L or (16 if args.workload == "krylov" else 30)
         D = args.D or (256 if args.workload == "krylov" else 1024)

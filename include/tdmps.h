@@ -197,6 +197,13 @@ tdmps_status tdmps_mps_apply_H(tdmps_mpo H, const double* alpha, tdmps_mps psi, 
 tdmps_status tdmps_mps_compress(int32_t nterms, const double* beta, const tdmps_mps* phi,
                                 const tdmps_fit_params* prm, tdmps_mps* out, tdmps_fit_info* info);
 
+/* One-particle reduced density matrix gamma_pq = sum_s <psi|a+_{ps} a_{qs}|psi> / <psi|psi>
+ * (the accuracy measure of the time-evolved states, H2O section) for all p, q in one
+ * left-to-right sweep over a right-canonical copy of psi (no truncation).  gamma: L*L
+ * interleaved complex, row-major (p, q), Hermitian, trace N.  TDMPS_ERR_NUMERIC for a zero
+ * state. */
+tdmps_status tdmps_mps_one_rdm(tdmps_mps psi, double* gamma);
+
 /* ---------------------------------------------------------------- time steps
  * Krylov step (Eqs. (kry_orth)/(kry_non), (krylov_evo)): basis of m states, the first
  * psi/|psi|; each next one fitted from H phi^k (minus the projections on all previous

@@ -267,6 +267,20 @@ def norm2(v):
     return float(np.real(np.vdot(v, v)))
 
 
+def one_rdm(space: Space, v, E=None):
+    """One-particle reduced density matrix gamma_pq = <v|E_pq|v> / <v|v> with the spin-summed
+    E_pq = sum_s a^+_{ps} a_{qs} (the accuracy measure of the H2O section), by its definition:
+    one expectation value per (p, q)."""
+    E = excitation_ops(space) if E is None else E
+    n2 = norm2(v)
+    L = space.L
+    g = np.zeros((L, L), dtype=np.complex128)
+    for p in range(L):
+        for q in range(L):
+            g[p, q] = np.vdot(v, E[p, q] @ v) / n2
+    return g
+
+
 def expectation(op, v):
     """<v|op|v> / <v|v> (the normalisation of c16: RK4 does not conserve the norm)."""
     return complex(np.vdot(v, op @ v)) / norm2(v)

@@ -408,6 +408,21 @@ extern "C" tdmps_status tdmps_mps_compress(int32_t nterms, const double* beta, c
   });
 }
 
+extern "C" tdmps_status tdmps_mps_one_rdm(tdmps_mps psi, double* gamma) {
+  return guard([&] {
+    TDMPS_REQUIRE(psi && gamma, TDMPS_ERR_ARG, "NULL argument");
+    tdmps_fit_params prm{};
+    prm.precision = TDMPS_FP64;
+    Contractor C = make_contractor(psi->ctx, &prm);
+    const std::vector<std::complex<double>> g = one_rdm(C, psi);
+    publish(psi->ctx, C);
+    for (size_t i = 0; i < g.size(); ++i) {
+      gamma[2 * i] = g[i].real();
+      gamma[2 * i + 1] = g[i].imag();
+    }
+  });
+}
+
 extern "C" tdmps_status tdmps_krylov_step(tdmps_mpo H, tdmps_mps psi, double dt, int32_t m, int32_t flags,
                                           const tdmps_fit_params* prm, tdmps_mps* out, double* Nmat, double* Hmat) {
   return guard([&] {

@@ -18,4 +18,7 @@ Mps* krylov_step(Contractor& C, const MpoHost* H, const Mps* psi, double dt, int
                  const tdmps_fit_params& prm, std::vector<std::complex<double>>* N,
                  std::vector<std::complex<double>>* Hm);
 
+// gamma_pq = sum_s <psi|a+_{ps} a_{qs}|psi> / <psi|psi>, L*L row-major.
+std::vector<std::complex<double>> one_rdm(Contractor& C, const Mps* psi);
+
 }  // namespace tdmps

@@ -220,6 +220,19 @@ struct Builder {
 
 }  // namespace
 
+int mpo_channel_kind(uint64_t key, int* so, int* op) {
+  const int t = key_type(key);
+  if (t == K_I) return 0;
+  if (t == K_H) return 1;
+  if (t == K_L1 && key_a(key) && !key_b(key)) {
+    const uint32_t code = key_a(key) - 1;
+    *so = (int)(code >> 2);
+    *op = (code & 3) == OP_C ? 0 : ((code & 3) == OP_A ? 1 : 2);
+    return 2;
+  }
+  return 3;
+}
+
 MpoHost build_mpo(int L, const double* h, const double* eri, double e0, bool two_body) {
   TDMPS_REQUIRE(L >= 2 && L <= 64, TDMPS_ERR_ARG, "L must be in [2, 64]");
   for (int64_t i = 0; i < (int64_t)L * L; ++i)

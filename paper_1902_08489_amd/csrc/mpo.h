@@ -48,6 +48,10 @@ struct MpoHost {
 };
 
 MpoHost build_mpo(int L, const double* h, const double* eri, double e0, bool two_body);
+// Kind of a channel (from MpoCut::key): 0 = identity so far, 1 = complete (H), 2 = one open
+// operator left of the cut (*so = spin orbital 2p + spin, *op = 0 creator / 1 annihilator),
+// 3 = anything else.
+int mpo_channel_kind(uint64_t key, int* so, int* op);
 void mpo_set_one_body(MpoHost& m, const double* h);
 void mpo_to_dense(const MpoHost& m, double* out);
 double mpo_det_element(const MpoHost& m, const uint8_t* bra, const uint8_t* ket);

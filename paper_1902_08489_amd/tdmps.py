@@ -89,6 +89,7 @@ _SIGS = {
     "tdmps_mps_apply_H": (ct.c_int32, [_P, _D, _P, ct.c_int32, _D, _PP, ct.POINTER(FitParams), _PP,
                                        ct.POINTER(FitInfo)]),
     "tdmps_mps_compress": (ct.c_int32, [ct.c_int32, _D, _PP, ct.POINTER(FitParams), _PP, ct.POINTER(FitInfo)]),
+    "tdmps_mps_one_rdm": (ct.c_int32, [_P, _D]),
     "tdmps_krylov_step": (ct.c_int32, [_P, _P, ct.c_double, ct.c_int32, ct.c_int32, ct.POINTER(FitParams), _PP,
                                        _D, _D]),
     "tdmps_rk4_step": (ct.c_int32, [_P, _P, _P, _P, ct.c_double, ct.POINTER(FitParams), _PP,
@@ -356,6 +357,13 @@ def compress(terms, params=None):
     _check(_LIB.tdmps_mps_compress(len(terms), _dp(beta), ct.cast(arr, _PP), ct.byref(params), ct.byref(out),
                                    ct.byref(info)))
     return MPS(out, terms[0][1].L), info
+
+
+def one_rdm(psi):
+    """gamma_pq = sum_s <psi|a+_{ps} a_{qs}|psi> / <psi|psi> as an (L, L) complex array."""
+    g = np.zeros(2 * psi.L * psi.L)
+    _check(_LIB.tdmps_mps_one_rdm(psi.h, _dp(g)))
+    return g.view(np.complex128).reshape(psi.L, psi.L)
 
 
 def krylov_step(H, psi, dt, m, orthogonal=True, params=None):

@@ -338,3 +338,19 @@ def test_per_block_launches_reproduce_grouped_launch(ctx, sys6):
         out, _ = T.apply_H(sys6.mpo, 1.0, psi, params=prm)
         outs.append(dense(out))
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("fixture,D", [("sys6", 30), ("sys8", 20)])
+def test_one_rdm_matches_oracle(ctx, request, fixture, D):
+    """One-particle reduced density matrix of random complex states (and of a determinant):
+    the one-sweep library result against the oracle's definition on the dense vector."""
+    s = request.getfixturevalue(fixture)
+    Nu, Nd = s.Q
+    bonds, data = synth.random_state(s.L, Nu, Nd, D, seed=17)
+    psi = T.MPS.from_blocks(ctx, bonds, data)
+    got = T.one_rdm(psi)
+    want = fci.one_rdm(s.space, s.space.restrict(om.to_full(blocks_to_oracle(bonds, data))))
+    assert np.abs(got - want).max() < 1e-12 * np.abs(want).max()
+    det = T.MPS.from_determinant(ctx, s.occ)
+    n = np.array([(int(o) & 1) + ((int(o) >> 1) & 1) for o in s.occ], float)
+    assert np.abs(T.one_rdm(det) - np.diag(n)).max() < 1e-13

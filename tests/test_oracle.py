@@ -99,6 +99,34 @@ def test_free_fermion_dipole_closed_form():
         assert abs(got - want) < 1e-11
 
 
+def test_one_rdm_pins():
+    """gamma_pq = <E_pq>: a determinant gives diag(n_p); with V = 0 the time-evolved matrix is
+    conj(U) gamma(0) U^T, U = exp(-iht) (index order of gamma_pq = <a+_p a_q>); for an
+    interacting state it is Hermitian with trace N and eigenvalues in [0, 2]."""
+    L = 6
+    h, eri, _ = synth.integrals(L)
+    occ = synth.ionized_determinant(L, 6)
+    space = fci.Space.sector(L, *synth.occ_charge(occ))
+    psi0 = np.zeros(space.dim, complex)
+    psi0[space.lookup(fci.mask_from_occ(occ))[0]] = 1
+    g0 = fci.one_rdm(space, psi0)
+    n = np.array([(int(o) & 1) + ((int(o) >> 1) & 1) for o in occ], float)
+    assert np.abs(g0 - np.diag(n)).max() < 1e-15
+    H0 = fci.hamiltonian(space, h, np.zeros((L,) * 4))
+    w, V = np.linalg.eigh(h)
+    for t in (0.3, 1.7):
+        g = fci.one_rdm(space, propagate.exact(H0, psi0, t))
+        U = V @ np.diag(np.exp(-1j * w * t)) @ V.conj().T
+        assert np.abs(g - U.conj() @ g0 @ U.T).max() < 1e-11
+    H = fci.hamiltonian(space, h, eri)
+    g = fci.one_rdm(space, propagate.exact(H, psi0, 0.9))
+    assert np.abs(g - g.conj().T).max() < 1e-13
+    assert abs(np.trace(g).real - n.sum()) < 1e-12
+    ev = np.linalg.eigvalsh(g)
+    assert ev.min() > -1e-12 and ev.max() < 2 + 1e-12
+    assert np.abs(g.imag).max() > 1e-6  # a time-evolved state has a complex matrix
+
+
 def test_rk4_map_is_taylor4():
     """Eq. (rk_add): the RK4 map equals the 4th-order Taylor polynomial of exp(-iH dt)."""
     L = 4
