@@ -20,6 +20,9 @@ Other workloads of the benchmark set (each prints its own JSON line; not the def
                         (default L = 16, D = 256, 200 steps of 0.02, checkpoints every 20)
   --workload rdm        one-particle reduced density matrix of a state in one sweep
                         (default L = 16, D = 256)
+  --workload green      Green's function G_ii(tau) of Eq. (green_time) on an H10-like chain:
+                        Krylov ground state, ionisation, backward Krylov steps (default
+                        L = 10, N = 10, D = 30, m = 5, dt = 0.05, i = 4)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32|bf16x3]
        [--krylov 0|1] [--no-cpu-baseline] [--check N] [--workload heff|krylov|precision|gradient]
@@ -89,7 +92,8 @@ def main():
                     help="copy 1 GiB device to device once before timing (reference for HBM byte counters)")
     ap.add_argument("--L", type=int, default=None)
     ap.add_argument("--D", type=int, default=None)
-    ap.add_argument("--workload", default="heff", choices=["heff", "krylov", "precision", "gradient", "rdm"])
+    ap.add_argument("--workload", default="heff",
+                    choices=["heff", "krylov", "precision", "gradient", "rdm", "green"])
     ap.add_argument("--dt", type=float, default=None)
     ap.add_argument("--sweeps", type=int, default=1, help="fit sweeps per H application (Krylov workloads)")
     ap.add_argument("--rk4-steps", type=int, default=200)
@@ -306,6 +310,39 @@ def other_workload(args, progress):
     ctx = T.Context(0, stream=side.cuda_stream)
     line = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "data": "synthetic (seeded integrals and block-sparse state)"}
+    if args.workload == "green":
+        L = args.L or 10
+        D = args.D or 30
+        nu, nd = L // 2, L - L // 2
+        dt = args.dt or 0.05
+        m = args.krylov_m if args.krylov_m != 12 else 5
+        h, eri, _ = synth.integrals(L, 1.0)
+        H = T.MPO.from_integrals(ctx, h, eri, 0.0)
+        guess = T.MPS.from_determinant(ctx, synth.determinant(L, nu, nd, seed=L))
+        t0 = time.perf_counter()
+        psi0, E0 = T.krylov_ground(H, guess, 8, 6, T.fit_params(Dmax=max(D, 64), n_sweeps=2))
+        t_gs = time.perf_counter() - t0
+        progress(f"ground state E0 = {E0:.10f} in {t_gs:.1f} s")
+        i = min(4, L - 1)
+        prm = T.fit_params(Dmax=D, n_sweeps=1)
+        ci = [T.annihilate(psi0, i, s) for s in (0, 1)]
+        phi = [T.annihilate(psi0, i, s) for s in (0, 1)]
+        den = sum(T.overlap(a, b) for a, b in zip(ci, phi))
+        G = [complex(-1j * den / den)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            phi = [T.krylov_step(H, p, -dt, m, True, prm)[0] for p in phi]
+            G.append(complex(-1j * sum(T.overlap(a, b) for a, b in zip(ci, phi)) / den))
+        dt_step = (time.perf_counter() - t0) / args.steps
+        line.update({"metric": f"Green's function steps/s @L={L} D={D} m={m}", "value": 1.0 / dt_step, "unit": "steps/s",
+                     "ms_per_step": dt_step * 1e3, "dtype": "fp64",
+                     "config": {"workload": f"G_ii(tau), i={i}, of the Krylov ground state, L={L} N={L} D={D} m={m} "
+                                            f"dt={dt} (both spins propagated per step)"},
+                     "ground_state_energy": E0, "ground_state_seconds": t_gs,
+                     "G_imag_last": G[-1].imag, "G_real_last": G[-1].real})
+        print(json.dumps(line), flush=True)
+        return
     if args.workload == "rdm":
         L = args.L or 16
         D = args.D or 256

@@ -204,6 +204,20 @@ tdmps_status tdmps_mps_compress(int32_t nterms, const double* beta, const tdmps_
  * state. */
 tdmps_status tdmps_mps_one_rdm(tdmps_mps psi, double* gamma);
 
+/* c_{site, spin}|psi> exactly (spin 0 = up, 1 = down), the ionisation step of the Green's
+ * function of Eq. (green_time): the site tensors left of site take the Jordan-Wigner sign,
+ * site takes the local annihilator, the bonds right of site lose the removed charge.  The
+ * result is a new state in the sector with one electron of that spin less (no truncation).
+ * TDMPS_ERR_SECTOR if psi has no electron of that spin, TDMPS_ERR_ARG for site/spin out of
+ * range. */
+tdmps_status tdmps_mps_annihilate(tdmps_mps psi, int32_t site, int32_t spin, tdmps_mps* out);
+/* Ground state by restarted Krylov (Lanczos) iterations on the same kernels as the time step
+ * (the initial state psi_0 of Eq. (green_time)): each restart builds an orthogonal Krylov
+ * basis of m states from the current iterate and replaces it by the normalised lowest Ritz
+ * state; energy (nullable) receives the last Ritz value.  TDMPS_ERR_ARG for restarts < 1. */
+tdmps_status tdmps_krylov_ground(tdmps_mpo H, tdmps_mps psi, int32_t m, int32_t restarts,
+                                 const tdmps_fit_params* prm, tdmps_mps* out, double* energy);
+
 /* ---------------------------------------------------------------- time steps
  * Krylov step (Eqs. (kry_orth)/(kry_non), (krylov_evo)): basis of m states, the first
  * psi/|psi|; each next one fitted from H phi^k (minus the projections on all previous

@@ -131,6 +131,20 @@ def hop_matrix(space: Space, i: int, j: int):
     return sp.csr_matrix((vals, (dst, src)), shape=(space.dim, space.dim))
 
 
+def annihilator(src: Space, dst: Space, j: int):
+    """Sparse matrix of a_j (spin orbital j) from `src` to `dst` (the sector with one electron
+    of that spin less), with the sign (-1)^{#occupied k < j} of the module convention."""
+    m = src.masks
+    occ = ((m >> j) & 1) == 1
+    cols = np.nonzero(occ)[0]
+    m0 = m[cols]
+    rows, found = dst.lookup(m0 ^ (1 << j))
+    if not np.all(found):
+        raise ValueError("destination space does not hold a_j |src>")
+    vals = np.where(popcount(m0 & ((1 << j) - 1)) % 2 == 0, 1.0, -1.0)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(dst.dim, src.dim))
+
+
 def excitation_ops(space: Space):
     """Spin-summed E_pq = sum_s a^+_{2p+s} a_{2q+s} for all p, q."""
     L = space.L

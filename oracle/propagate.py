@@ -160,3 +160,34 @@ def dipole_response_gradient(H0, M, mu, psi0, f, A, dt, nsteps):
             grad += 2 * dt * f(ts[s]) * (kb.conj() @ (M @ u)).imag
         lam = lam + ub2 + ub3 + ub4 + adj(0, kb1)
     return float(D), float(grad)
+
+
+# ---------------------------------------------------------------- Green's function
+# Eq. (green_time): G_ij(tau) = -i sum_s <psi0|c+_{is} e^{iH tau} c_{js}|psi0> / sum_s <psi0|c+_{is} c_{js}|psi0>,
+# the ionised state c_{js} psi0 propagated backwards in time and projected on c_{is} psi0.
+def green_function(L, h, eri, space, nu, nd, psi0, i, j, taus, step=None):
+    """G_ij at the times `taus` from the dense vector psi0 on `space`, the (nu, nd) sector.
+    step(H, v, dtau) advances v by dtau backwards in time (default: exact exp(+iH dtau)); the
+    taus must then be multiples of one step size, starting at 0."""
+    from . import fci
+    num = np.zeros(len(taus), complex)
+    den = 0.0 + 0.0j
+    for s in (0, 1):
+        if (nu, nd)[s] == 0:
+            continue
+        dst = fci.Space.sector(L, nu - (s == 0), nd - (s == 1))
+        Hd = fci.hamiltonian(dst, h, eri)
+        ci = fci.annihilator(space, dst, 2 * i + s) @ psi0
+        v = fci.annihilator(space, dst, 2 * j + s) @ psi0
+        den += np.vdot(ci, v)
+        prev = 0.0
+        for k, t in enumerate(taus):
+            if step is None:
+                w = exact(Hd, v, -t)
+            else:
+                if k > 0:
+                    v = step(Hd, v, t - prev)
+                w = v
+            prev = t
+            num[k] += np.vdot(ci, w)
+    return -1j * num / den

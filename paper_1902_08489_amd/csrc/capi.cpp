@@ -408,6 +408,30 @@ extern "C" tdmps_status tdmps_mps_compress(int32_t nterms, const double* beta, c
   });
 }
 
+extern "C" tdmps_status tdmps_mps_annihilate(tdmps_mps psi, int32_t site, int32_t spin, tdmps_mps* out) {
+  return guard([&] {
+    TDMPS_REQUIRE(psi && out, TDMPS_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    dev_bind(psi->ctx->device, psi->ctx->stream);
+    *out = mps_annihilate(psi->ctx, psi, site, spin);
+  });
+}
+
+extern "C" tdmps_status tdmps_krylov_ground(tdmps_mpo H, tdmps_mps psi, int32_t m, int32_t restarts,
+                                            const tdmps_fit_params* prm, tdmps_mps* out, double* energy) {
+  return guard([&] {
+    TDMPS_REQUIRE(H && psi && out, TDMPS_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    check_prm(prm);
+    Contractor C = make_contractor(psi->ctx, prm);
+    double E = 0;
+    Mps* r = krylov_ground(C, &H->host, psi, m, restarts, *prm, &E);
+    publish(psi->ctx, C);
+    if (energy) *energy = E;
+    *out = r;
+  });
+}
+
 extern "C" tdmps_status tdmps_mps_one_rdm(tdmps_mps psi, double* gamma) {
   return guard([&] {
     TDMPS_REQUIRE(psi && gamma, TDMPS_ERR_ARG, "NULL argument");

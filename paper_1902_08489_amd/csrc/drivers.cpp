@@ -59,17 +59,21 @@ void herm_eig(int n, std::vector<zd> A, std::vector<double>& w, std::vector<zd>&
 
 }  // namespace
 
-std::vector<zd> krylov_coefficients(int m, const std::vector<zd>& Nin, const std::vector<zd>& Hin, double dt,
-                                    bool orthogonal) {
+namespace {
+
+// Generalised Hermitian eigenproblem of the Krylov matrices, H V = N V diag(lam), V^H N V = 1,
+// on the directions where N is not numerically singular (orthogonal mode: all of them).
+void krylov_eig(int m, const std::vector<zd>& Nin, const std::vector<zd>& Hin, bool orthogonal, std::vector<zd>& V,
+                std::vector<double>& lam, int& r, std::vector<zd>& Nsym) {
   std::vector<zd> N(Nin), H(Hin);
-  for (int r = 0; r < m; ++r)
-    for (int c = r; c < m; ++c) {
-      zd a = 0.5 * (N[r * m + c] + std::conj(N[c * m + r]));
-      N[r * m + c] = a;
-      N[c * m + r] = std::conj(a);
-      zd b = 0.5 * (H[r * m + c] + std::conj(H[c * m + r]));
-      H[r * m + c] = b;
-      H[c * m + r] = std::conj(b);
+  for (int a = 0; a < m; ++a)
+    for (int c = a; c < m; ++c) {
+      zd x = 0.5 * (N[a * m + c] + std::conj(N[c * m + a]));
+      N[a * m + c] = x;
+      N[c * m + a] = std::conj(x);
+      zd y = 0.5 * (H[a * m + c] + std::conj(H[c * m + a]));
+      H[a * m + c] = y;
+      H[c * m + a] = std::conj(y);
     }
   std::vector<double> nw;
   std::vector<zd> Q;
@@ -84,7 +88,7 @@ std::vector<zd> krylov_coefficients(int m, const std::vector<zd>& Nin, const std
     else
       TDMPS_REQUIRE(!orthogonal, TDMPS_ERR_SINGULAR, "Krylov overlap matrix is not positive definite");
   }
-  int r = (int)keep.size();
+  r = (int)keep.size();
   // X = Q_keep diag(n^-1/2): X^H N X = 1
   std::vector<zd> X((size_t)m * r);
   for (int a = 0; a < m; ++a)
@@ -97,23 +101,31 @@ std::vector<zd> krylov_coefficients(int m, const std::vector<zd>& Nin, const std
         for (int b = 0; b < m; ++b) s += std::conj(X[a * r + i]) * H[a * m + b] * X[b * r + j];
       Hp[i * r + j] = s;
     }
-  std::vector<double> lam;
   std::vector<zd> Y;
   herm_eig(r, Hp, lam, Y);
-  // V = X Y;  c = V exp(-i dt lam) V^H N e0
-  std::vector<zd> V((size_t)m * r, zd(0));
+  V.assign((size_t)m * r, zd(0));
   for (int a = 0; a < m; ++a)
     for (int j = 0; j < r; ++j) {
       zd s = 0;
       for (int i = 0; i < r; ++i) s += X[a * r + i] * Y[i * r + j];
       V[a * r + j] = s;
     }
-  std::vector<zd> Ne0(m);
-  for (int a = 0; a < m; ++a) Ne0[a] = N[a * m + 0];
+  Nsym = N;
+}
+
+}  // namespace
+
+std::vector<zd> krylov_coefficients(int m, const std::vector<zd>& Nin, const std::vector<zd>& Hin, double dt,
+                                    bool orthogonal) {
+  std::vector<zd> V, N;
+  std::vector<double> lam;
+  int r = 0;
+  krylov_eig(m, Nin, Hin, orthogonal, V, lam, r, N);
+  // c = V exp(-i dt lam) V^H N e0
   std::vector<zd> y(r);
   for (int j = 0; j < r; ++j) {
     zd s = 0;
-    for (int a = 0; a < m; ++a) s += std::conj(V[a * r + j]) * Ne0[a];
+    for (int a = 0; a < m; ++a) s += std::conj(V[a * r + j]) * N[a * m + 0];
     y[j] = s * std::exp(zd(0, -dt * lam[j]));
   }
   std::vector<zd> c(m);
@@ -122,6 +134,21 @@ std::vector<zd> krylov_coefficients(int m, const std::vector<zd>& Nin, const std
     for (int j = 0; j < r; ++j) s += V[a * r + j] * y[j];
     c[a] = s;
   }
+  return c;
+}
+
+std::vector<zd> krylov_lowest(int m, const std::vector<zd>& Nin, const std::vector<zd>& Hin, bool orthogonal,
+                              double* energy) {
+  std::vector<zd> V, N;
+  std::vector<double> lam;
+  int r = 0;
+  krylov_eig(m, Nin, Hin, orthogonal, V, lam, r, N);
+  int jmin = 0;
+  for (int j = 1; j < r; ++j)
+    if (lam[j] < lam[jmin]) jmin = j;
+  if (energy) *energy = lam[jmin];
+  std::vector<zd> c(m);
+  for (int a = 0; a < m; ++a) c[a] = V[a * r + jmin];
   return c;
 }
 
@@ -164,20 +191,37 @@ Mps* rk4_step(Contractor& C, const MpoHost* Ht, const MpoHost* Hm, const MpoHost
   return out;
 }
 
-Mps* krylov_step(Contractor& C, const MpoHost* H, const Mps* psi, double dt, int m, bool orthogonal,
-                 const tdmps_fit_params& prm, std::vector<zd>* Nout, std::vector<zd>* Hout) {
+// Krylov basis of Eqs. (kry_orth)/(kry_non): phi^0 = psi/|psi|, each next vector fitted from
+// H phi^k (minus the projections on all previous vectors in the orthogonal mode) and
+// normalised; N and H (m x m, row-major) from overlaps and sandwiches.  The orthogonal basis
+// stops early when the space is invariant: when the component of H phi^k orthogonal to the
+// basis is below 1e-10 of H phi^k (e.g. psi an eigenstate), only meff = k + 1 vectors are
+// kept (unused rows and columns of N and H stay 0).
+struct KrylovBasis {
+  std::vector<std::unique_ptr<Mps>> phi;
+  std::vector<zd> N, H;
+  int meff = 0;
+  double s0 = 0;  // |psi|
+};
+
+static KrylovBasis krylov_basis(Contractor& C, const MpoHost* H, const Mps* psi, int m, bool orthogonal,
+                                const tdmps_fit_params& prm) {
   TDMPS_REQUIRE(m >= 2 && m <= 64, TDMPS_ERR_ARG, "Krylov dimension must be in [2, 64]");
   auto z = [](cplx c) { return zd(c.x, c.y); };
   // optional progress lines on stderr (TDMPS_PROGRESS set): one per Krylov vector
   const bool progress = std::getenv("TDMPS_PROGRESS") != nullptr;
   const double t_start = wall_seconds();
+  KrylovBasis K;
   double n0 = overlap(C, psi, psi).x;
   TDMPS_REQUIRE(n0 > 0 && std::isfinite(n0), TDMPS_ERR_NUMERIC, "state has zero or non-finite norm");
-  double s0 = std::sqrt(n0);
-  std::vector<std::unique_ptr<Mps>> phi;
+  K.s0 = std::sqrt(n0);
+  auto& phi = K.phi;
   phi.emplace_back(mps_clone(psi));
-  scale_mps(C.ctx, phi[0].get(), cplx{1.0 / s0, 0.0});
-  std::vector<zd> N((size_t)m * m, zd(0)), Hm((size_t)m * m, zd(0));
+  scale_mps(C.ctx, phi[0].get(), cplx{1.0 / K.s0, 0.0});
+  std::vector<zd>& N = K.N;
+  std::vector<zd>& Hm = K.H;
+  N.assign((size_t)m * m, zd(0));
+  Hm.assign((size_t)m * m, zd(0));
   N[0] = z(overlap(C, phi[0].get(), phi[0].get()));
   MpoHost I = identity_mpo(psi->L);
   auto bras = [&](int n) {
@@ -185,9 +229,6 @@ Mps* krylov_step(Contractor& C, const MpoHost* H, const Mps* psi, double dt, int
     for (int j = 0; j < n; ++j) b.push_back(phi[j].get());
     return b;
   };
-  // The orthogonal basis stops early if the space is invariant: when the component of
-  // H phi^k orthogonal to the basis is below 1e-10 of H phi^k (e.g. psi an eigenstate), the
-  // step uses the k + 1 vectors found so far (unused rows and columns of N and H stay 0).
   int meff = m;
   for (int k = 0; k < m - 1; ++k) {
     // H_jk = <phi_j|H|phi_k> for all j <= k in one batched sweep
@@ -229,19 +270,56 @@ Mps* krylov_step(Contractor& C, const MpoHost* H, const Mps* psi, double dt, int
       Hm[(m - 1) * m + j] = std::conj(Hm[j * m + m - 1]);
     }
   }
-  std::vector<zd> Ns((size_t)meff * meff), Hs((size_t)meff * meff);
-  for (int r = 0; r < meff; ++r)
-    for (int q = 0; q < meff; ++q) {
-      Ns[r * meff + q] = N[r * m + q];
-      Hs[r * meff + q] = Hm[r * m + q];
+  K.meff = meff;
+  return K;
+}
+
+static void sub_matrices(const KrylovBasis& K, int m, std::vector<zd>& Ns, std::vector<zd>& Hs) {
+  const int e = K.meff;
+  Ns.assign((size_t)e * e, zd(0));
+  Hs.assign((size_t)e * e, zd(0));
+  for (int r = 0; r < e; ++r)
+    for (int q = 0; q < e; ++q) {
+      Ns[r * e + q] = K.N[r * m + q];
+      Hs[r * e + q] = K.H[r * m + q];
     }
-  auto c = krylov_coefficients(meff, Ns, Hs, dt, orthogonal);
+}
+
+Mps* krylov_step(Contractor& C, const MpoHost* H, const Mps* psi, double dt, int m, bool orthogonal,
+                 const tdmps_fit_params& prm, std::vector<zd>* Nout, std::vector<zd>* Hout) {
+  KrylovBasis K = krylov_basis(C, H, psi, m, orthogonal, prm);
+  std::vector<zd> Ns, Hs;
+  sub_matrices(K, m, Ns, Hs);
+  auto c = krylov_coefficients(K.meff, Ns, Hs, dt, orthogonal);
   std::vector<FitTerm> terms;
-  for (int k = 0; k < meff; ++k) terms.push_back({cplx{s0 * c[k].real(), s0 * c[k].imag()}, phi[k].get()});
+  for (int k = 0; k < K.meff; ++k)
+    terms.push_back({cplx{K.s0 * c[k].real(), K.s0 * c[k].imag()}, K.phi[k].get()});
   Mps* out = fit(C, nullptr, cplx{1, 0}, nullptr, terms, prm, nullptr);
-  if (Nout) *Nout = N;
-  if (Hout) *Hout = Hm;
+  if (Nout) *Nout = K.N;
+  if (Hout) *Hout = K.H;
   return out;
+}
+
+Mps* krylov_ground(Contractor& C, const MpoHost* H, const Mps* psi, int m, int restarts, const tdmps_fit_params& prm,
+                   double* energy) {
+  TDMPS_REQUIRE(restarts >= 1, TDMPS_ERR_ARG, "need at least one restart");
+  std::unique_ptr<Mps> cur(mps_clone(psi));
+  double E = 0;
+  for (int r = 0; r < restarts; ++r) {
+    KrylovBasis K = krylov_basis(C, H, cur.get(), m, true, prm);
+    std::vector<zd> Ns, Hs;
+    sub_matrices(K, m, Ns, Hs);
+    auto c = krylov_lowest(K.meff, Ns, Hs, true, &E);
+    std::vector<FitTerm> terms;
+    for (int k = 0; k < K.meff; ++k) terms.push_back({cplx{c[k].real(), c[k].imag()}, K.phi[k].get()});
+    std::unique_ptr<Mps> nxt(fit(C, nullptr, cplx{1, 0}, nullptr, terms, prm, nullptr));
+    const double nn = overlap(C, nxt.get(), nxt.get()).x;
+    TDMPS_REQUIRE(nn > 0 && std::isfinite(nn), TDMPS_ERR_NUMERIC, "ground-state iterate vanished");
+    scale_mps(C.ctx, nxt.get(), cplx{1.0 / std::sqrt(nn), 0.0});
+    cur = std::move(nxt);
+  }
+  if (energy) *energy = E;
+  return cur.release();
 }
 
 }  // namespace tdmps

@@ -424,6 +424,77 @@ void mps_from_det(Mps* m, const uint8_t* occ) {
   }
 }
 
+Mps* mps_annihilate(Ctx* ctx, const Mps* psi, int j, int sigma) {
+  const int L = psi->L;
+  TDMPS_REQUIRE(j >= 0 && j < L && (sigma == 0 || sigma == 1), TDMPS_ERR_ARG, "site or spin out of range");
+  const Charge e = sigma == 0 ? Charge(1, 0) : Charge(0, 1);
+  auto has = [&](Charge q) { return sigma == 0 ? q.nu >= 1 : q.nd >= 1; };
+  TDMPS_REQUIRE(has(psi->total), TDMPS_ERR_SECTOR, "the state has no electron of that spin");
+  // bonds left of site j (cuts <= j) are kept; right of it every charge loses e, and sectors
+  // without an electron of spin sigma left of the cut cannot survive the annihilation
+  std::vector<Bond> nb(L + 1);
+  std::vector<std::vector<int>> map(L + 1);
+  for (int c = 0; c <= L; ++c) {
+    const Bond& b = psi->bond[c];
+    map[c].assign(b.nsec(), -1);
+    for (int s = 0; s < b.nsec(); ++s) {
+      if (c <= j) {
+        map[c][s] = nb[c].nsec();
+        nb[c].q.push_back(b.q[s]);
+        nb[c].dim.push_back(b.dim[s]);
+      } else if (has(b.q[s])) {
+        map[c][s] = nb[c].nsec();
+        nb[c].q.push_back(b.q[s] - e);
+        nb[c].dim.push_back(b.dim[s]);
+      }
+    }
+  }
+  Mps* m = mps_new(ctx, L, nb);
+  try {
+    int maxd = 1;
+    for (auto& b : psi->bond)
+      for (int d : b.dim) maxd = std::max(maxd, d);
+    Staging st;
+    const double* minus = st.put(ctx, std::vector<double>((size_t)maxd, -1.0));
+    CopyPlan cp;
+    for (int k = 0; k < L; ++k) {
+      const SiteLayout& ol = psi->lay[k];
+      const SiteLayout& nl = m->lay[k];
+      const Bond& bl = psi->bond[k];
+      const Bond& br = psi->bond[k + 1];
+      for (int a = 0; a < bl.nsec(); ++a) {
+        const int na = map[k][a];
+        if (na < 0) continue;
+        for (int n = 0; n < 4; ++n) {
+          const int b = ol.rs[a][n];
+          if (b < 0) continue;
+          int n2 = n;
+          bool neg = false;
+          if (k < j) {
+            neg = local_parity(n) == 1;  // Jordan-Wigner string
+          } else if (k == j) {
+            if (!((n >> sigma) & 1)) continue;
+            n2 = n ^ (1 << sigma);
+            neg = sigma == 1 && (n & 1);  // the down operator passes the up electron of the site
+          }
+          const int b2 = map[k + 1][b];
+          if (b2 < 0) continue;
+          TDMPS_REQUIRE(nl.rs[na][n2] == b2, TDMPS_ERR_NUMERIC, "internal: annihilated block sector");
+          cp.add(psi->site[k].c() + ol.panel_off[a] + ol.col[a][n], ol.width[a], 1,
+                 m->site[k].c() + nl.panel_off[na] + nl.col[na][n2], nl.width[na], bl.dim[a], br.dim[b], 0, nullptr,
+                 nullptr, neg ? minus : nullptr, nullptr);
+        }
+      }
+    }
+    cp.run(ctx);
+    dev_sync(ctx->stream);
+  } catch (...) {
+    delete m;
+    throw;
+  }
+  return m;
+}
+
 MpoHost identity_mpo(int L) {
   MpoHost M;
   M.L = L;

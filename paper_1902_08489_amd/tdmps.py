@@ -89,6 +89,8 @@ _SIGS = {
     "tdmps_mps_apply_H": (ct.c_int32, [_P, _D, _P, ct.c_int32, _D, _PP, ct.POINTER(FitParams), _PP,
                                        ct.POINTER(FitInfo)]),
     "tdmps_mps_compress": (ct.c_int32, [ct.c_int32, _D, _PP, ct.POINTER(FitParams), _PP, ct.POINTER(FitInfo)]),
+    "tdmps_mps_annihilate": (ct.c_int32, [_P, ct.c_int32, ct.c_int32, _PP]),
+    "tdmps_krylov_ground": (ct.c_int32, [_P, _P, ct.c_int32, ct.c_int32, ct.POINTER(FitParams), _PP, _D]),
     "tdmps_mps_one_rdm": (ct.c_int32, [_P, _D]),
     "tdmps_krylov_step": (ct.c_int32, [_P, _P, ct.c_double, ct.c_int32, ct.c_int32, ct.POINTER(FitParams), _PP,
                                        _D, _D]),
@@ -357,6 +359,21 @@ def compress(terms, params=None):
     _check(_LIB.tdmps_mps_compress(len(terms), _dp(beta), ct.cast(arr, _PP), ct.byref(params), ct.byref(out),
                                    ct.byref(info)))
     return MPS(out, terms[0][1].L), info
+
+
+def annihilate(psi, site, spin):
+    """c_{site, spin} psi (spin 0 = up, 1 = down), exact."""
+    out = ct.c_void_p()
+    _check(_LIB.tdmps_mps_annihilate(psi.h, int(site), int(spin), ct.byref(out)))
+    return MPS(out, psi.L)
+
+
+def krylov_ground(H, psi, m, restarts, params=None):
+    """Ground state by restarted Krylov iterations: (state, energy)."""
+    params = params or fit_params()
+    out, e = ct.c_void_p(), np.zeros(1)
+    _check(_LIB.tdmps_krylov_ground(H.h, psi.h, int(m), int(restarts), ct.byref(params), ct.byref(out), _dp(e)))
+    return MPS(out, psi.L), float(e[0])
 
 
 def one_rdm(psi):

@@ -354,3 +354,55 @@ def test_one_rdm_matches_oracle(ctx, request, fixture, D):
     det = T.MPS.from_determinant(ctx, s.occ)
     n = np.array([(int(o) & 1) + ((int(o) >> 1) & 1) for o in s.occ], float)
     assert np.abs(T.one_rdm(det) - np.diag(n)).max() < 1e-13
+
+
+def test_annihilate_matches_oracle(ctx, sys6):
+    """c_{site, spin}|psi> of a random complex state against the oracle's annihilator on the
+    dense vector, for both spins and several sites; an empty spin channel raises."""
+    Nu, Nd = sys6.Q
+    bonds, data = synth.random_state(6, Nu, Nd, 30, seed=23)
+    psi = T.MPS.from_blocks(ctx, bonds, data)
+    v = sys6.space.restrict(om.to_full(blocks_to_oracle(bonds, data)))
+    for site, spin in ((0, 0), (2, 1), (5, 0), (3, 1)):
+        got = T.annihilate(psi, site, spin)
+        dst = fci.Space.sector(6, Nu - (spin == 0), Nd - (spin == 1))
+        want = fci.annihilator(sys6.space, dst, 2 * site + spin) @ v
+        assert rel(dst.restrict(got.to_dense()), want) < 1e-13
+    empty = T.MPS.from_determinant(ctx, np.array([1, 0, 1, 0, 0, 0], np.uint8))  # two up electrons
+    with pytest.raises(T.TdmpsError):
+        T.annihilate(empty, 0, 1)
+
+
+def test_krylov_ground_state_and_green_function(ctx):
+    """Eq. (green_time) at L = 6, N = 6: restarted Krylov ground state against exact
+    diagonalisation, then G_ij(tau) over three backward Krylov steps (D >= D_FCI everywhere)
+    against the oracle's definition with the dense Krylov map on the library's ground state."""
+    L, nu, nd = 6, 3, 3
+    h, eri, _ = synth.integrals(L)
+    space = fci.Space.sector(L, nu, nd)
+    Hd = fci.hamiltonian(space, h, eri).toarray()
+    w, U = np.linalg.eigh(Hd)
+    mpo = T.MPO.from_integrals(ctx, h, eri, 0.0)
+    prm = T.fit_params(Dmax=100, n_sweeps=4)
+    guess = T.MPS.from_determinant(ctx, synth.determinant(L, nu, nd, seed=3))
+    psi0, E0 = T.krylov_ground(mpo, guess, 8, 6, prm)
+    v0 = space.restrict(psi0.to_dense())
+    assert abs(E0 - w[0]) < 1e-9 * abs(w[0])
+    assert abs(abs(np.vdot(U[:, 0], v0)) - 1) < 1e-8
+    dt, m, nsteps = 0.05, 5, 3
+    for i, j in ((2, 2), (1, 4)):
+        num = np.zeros(nsteps + 1, complex)
+        den = 0j
+        for s in (0, 1):
+            ci = T.annihilate(psi0, i, s)
+            phi = T.annihilate(psi0, j, s)
+            den += T.overlap(ci, phi)
+            num[0] += T.overlap(ci, phi)
+            for k in range(nsteps):
+                phi, _, _ = T.krylov_step(mpo, phi, -dt, m, True, prm)
+                num[k + 1] += T.overlap(ci, phi)
+        G = -1j * num / den
+        step = lambda H, v, d: propagate.krylov(lambda x: H @ x, v, -d, m)[0]
+        want = propagate.green_function(L, h, eri, space, nu, nd, v0, i, j, [k * dt for k in range(nsteps + 1)],
+                                        step=step)
+        assert np.abs(G - want).max() < 1e-9

@@ -127,6 +127,39 @@ def test_one_rdm_pins():
     assert np.abs(g.imag).max() > 1e-6  # a time-evolved state has a complex matrix
 
 
+def test_green_function_pins():
+    """Eq. (green_time) by definition (annihilate, propagate backwards exactly, project):
+    G_ij(0) = -i; for V = 0 and psi0 the ground state (a determinant of eigen-orbitals of h),
+    e^{iH tau} c_js e^{-iH tau} = sum_k (e^{-ih tau})_jk c_ks gives
+    sum_s <c_is psi0|e^{iH tau}|c_js psi0> = e^{iE0 tau} sum_s (e^{-ih tau} gamma_s^T)_ji with
+    gamma_s,ik = <a+_is a_ks> = sum_{n occupied} conj(V_in) V_kn."""
+    L = 5
+    h, eri, _ = synth.integrals(L)
+    nu, nd = 3, 2
+    space = fci.Space.sector(L, nu, nd)
+    H0 = fci.hamiltonian(space, h, np.zeros((L,) * 4)).toarray()
+    w, U = np.linalg.eigh(H0)
+    psi0, E0 = U[:, 0], w[0]
+    eps, V = np.linalg.eigh(h)
+    taus = [0.0, 0.4, 1.3]
+    for i, j in ((1, 1), (0, 3), (4, 2)):
+        G = propagate.green_function(L, h, np.zeros((L,) * 4), space, nu, nd, psi0, i, j, taus)
+        num = np.zeros(len(taus), complex)
+        den = 0.0
+        for n_occ in (nu, nd):
+            gam = V[:, :n_occ].conj() @ V[:, :n_occ].T  # gamma_ik = sum_n conj(V_in) V_kn
+            den += gam[i, j]
+            for k, t in enumerate(taus):
+                P = V @ np.diag(np.exp(-1j * eps * t)) @ V.conj().T  # e^{-ih tau}
+                num[k] += np.exp(1j * E0 * t) * (P @ gam.T)[j, i]
+        assert abs(G[0] + 1j) < 1e-12
+        assert np.abs(G - (-1j) * num / den).max() < 1e-10
+    # the spin-summed gamma of the closed form is the oracle's one-particle density matrix
+    g = fci.one_rdm(space, psi0)
+    want = V[:, :nu].conj() @ V[:, :nu].T + V[:, :nd].conj() @ V[:, :nd].T
+    assert np.abs(g - want).max() < 1e-12
+
+
 def test_rk4_map_is_taylor4():
     """Eq. (rk_add): the RK4 map equals the 4th-order Taylor polynomial of exp(-iH dt)."""
     L = 4
