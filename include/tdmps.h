@@ -147,6 +147,13 @@ tdmps_status tdmps_ctx_clear_tuning(tdmps_ctx ctx);
  * ctx may be NULL for a host-only operator (tdmps_mpo_to_dense, tdmps_mpo_det_element). */
 tdmps_status tdmps_mpo_from_integrals(tdmps_ctx ctx, int32_t L, const double* h, const double* eri,
                                       double e0, tdmps_mpo* out);
+/* Orbital order by a Fiedler reduction of the band width of the orbital coupling (the
+ * ordering of the molecular orbitals in the H2O section): coupling w_ij = |h_ij| + |(ij|ji)|
+ * for i != j (eri nullable: hopping only), orbitals sorted by the Fiedler vector of the graph
+ * Laplacian diag(sum_j w_ij) - w.  perm (L entries): position k of the new order holds old
+ * orbital perm[k]; reorder the integrals as h'[k][l] = h[perm[k]][perm[l]] (and likewise all
+ * four indices of eri) before building the MPO.  Host only; TDMPS_ERR_NUMERIC for NaN/Inf. */
+tdmps_status tdmps_fiedler_order(int32_t L, const double* h, const double* eri, int32_t* perm);
 /* One-body operator sum_pq t_pq a+_{p s} a_{q s} (e.g. the dipole operator). */
 tdmps_status tdmps_mpo_one_body(tdmps_ctx ctx, int32_t L, const double* t, tdmps_mpo* out);
 /* Replace the one-body integrals of an MPO in place (time-dependent H(t) = H0 + E(t) mu). */

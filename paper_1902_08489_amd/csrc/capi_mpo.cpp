@@ -32,6 +32,18 @@ extern "C" tdmps_status tdmps_mpo_from_integrals(tdmps_ctx ctx, int32_t L, const
   });
 }
 
+namespace tdmps {
+std::vector<int> fiedler_order(int L, const double* h, const double* eri);
+}
+
+extern "C" tdmps_status tdmps_fiedler_order(int32_t L, const double* h, const double* eri, int32_t* perm) {
+  return guard([&] {
+    TDMPS_REQUIRE(h && perm, TDMPS_ERR_ARG, "NULL argument");
+    const std::vector<int> p = tdmps::fiedler_order(L, h, eri);
+    for (int i = 0; i < L; ++i) perm[i] = p[i];
+  });
+}
+
 extern "C" tdmps_status tdmps_mpo_one_body(tdmps_ctx ctx, int32_t L, const double* t, tdmps_mpo* out) {
   return guard([&] {
     TDMPS_REQUIRE(out && t, TDMPS_ERR_ARG, "NULL argument");

@@ -69,6 +69,7 @@ _SIGS = {
     "tdmps_ctx_autotune": (ct.c_int32, [_P, ct.c_int32, _I32, _D]),
     "tdmps_ctx_clear_tuning": (ct.c_int32, [_P]),
     "tdmps_mpo_from_integrals": (ct.c_int32, [_P, ct.c_int32, _D, _D, ct.c_double, _PP]),
+    "tdmps_fiedler_order": (ct.c_int32, [ct.c_int32, _D, ct.c_void_p, _I32]),
     "tdmps_mpo_one_body": (ct.c_int32, [_P, ct.c_int32, _D, _PP]),
     "tdmps_mpo_set_one_body": (ct.c_int32, [_P, _D]),
     "tdmps_mpo_bond_dims": (ct.c_int32, [_P, _I32]),
@@ -359,6 +360,25 @@ def compress(terms, params=None):
     _check(_LIB.tdmps_mps_compress(len(terms), _dp(beta), ct.cast(arr, _PP), ct.byref(params), ct.byref(out),
                                    ct.byref(info)))
     return MPS(out, terms[0][1].L), info
+
+
+def fiedler_order(h, eri=None):
+    """Orbital permutation (new position -> old orbital) from the Fiedler vector of the
+    coupling |h_ij| + |(ij|ji)|."""
+    load()
+    L = h.shape[0]
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    e = None if eri is None else np.ascontiguousarray(eri, dtype=np.float64)
+    perm = np.zeros(L, dtype=np.int32)
+    _check(_LIB.tdmps_fiedler_order(L, _dp(h), None if e is None else e.ctypes.data_as(ct.c_void_p),
+                                    perm.ctypes.data_as(_I32)))
+    return perm
+
+
+def permute_integrals(h, eri, perm):
+    """Integrals in the new orbital order: h'[k, l] = h[perm[k], perm[l]], likewise eri."""
+    p = np.asarray(perm)
+    return h[np.ix_(p, p)], eri[np.ix_(p, p, p, p)]
 
 
 def annihilate(psi, site, spin):
