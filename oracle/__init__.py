@@ -18,4 +18,6 @@ that it follows):
                 decomposition; truncation to the D largest singular values; the
                 variational two-site fit of Eq. (add_min) computed by projection; RK4 and
                 Krylov drivers built from it.
+  ordering   -- Fiedler ordering of the orbitals (H2O section) and the relabelling of the
+                integrals.
 """
