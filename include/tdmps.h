@@ -97,7 +97,10 @@ tdmps_status tdmps_ctx_destroy(tdmps_ctx ctx);
 /* Counters of the last operation (fit, time step or expectation value), TDMPS_NCOUNTERS
  * doubles: out[0] = algorithmic flops of the H_eff contractions, out[1] = executed H_eff flops,
  * out[2..6] = wall seconds spent in H_eff, environment updates, SVD truncation (QR included),
- * premix and sandwiches (sandwich time includes its own environment updates and premix),
+ * premix and sandwiches (sandwich time includes its own environment updates and premix;
+ * launches are asynchronous, so GPU time is charged to the phase that next waits for the
+ * stream unless TDMPS_PHASE_TIMING was set when the context was created, which ends every
+ * phase with a synchronisation),
  * out[7] = executed environment-update flops, out[8] = executed premix flops, out[9] / out[10]
  * = Jacobi sweeps / rounds summed over the SVDs, out[11..14] = number of SVD truncations,
  * H_eff applications, environment updates and sandwiches, out[15] = seconds in the QR

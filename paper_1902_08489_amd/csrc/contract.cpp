@@ -17,6 +17,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <tuple>
 
 #include "engine.h"
@@ -41,22 +43,35 @@ struct MixRow {
   std::vector<std::pair<int, double>> src;  // (source channel, coefficient)
 };
 
-// With ext != nullptr the premix products are appended to *ext (run by the caller) instead
-// of being run here.
-SideOps build_ops(Contractor& C, const Env& E, const MpoHost& W, int site, bool left, GemmPlan* ext = nullptr) {
-  const double t0 = wall_seconds();
-  struct Acc {
-    Contractor& C;
-    double t0;
-    ~Acc() { C.t_mix += wall_seconds() - t0; }
-  } acc_{C, t0};
-  SideOps ops;
-  const int mid_cut = left ? site + 1 : site;
-  const MpoCut& mc = W.cut[mid_cut];
-  const MpoCut& sc = W.cut[E.cut];
-  ops.cut = mid_cut;
-  ops.env = &E;
-  ops.ch.resize(mc.size());
+// The environment-independent part of a premix: which channels of the middle cut alias an
+// environment channel and which are combinations, the combination groups and their dense
+// coefficient matrices (uploaded once).  It depends only on the operator's coefficients
+// (its version), the site and the side, so it is cached per (stream, version, site, side).
+struct SkelRef {
+  int grp = 0, idx = 0;
+  double coef = 0;
+  bool mix = false;
+};
+struct SkelChan {
+  std::vector<int> pat;
+  std::vector<SkelRef> ref;
+};
+struct PremixSkel {
+  struct Pend {
+    int g, cw, wlo, ncol;
+    size_t off;
+  };
+  std::vector<SkelChan> ch;
+  std::vector<std::pair<Charge, int>> groups;
+  std::vector<Pend> pend;
+  std::shared_ptr<DevBuf> wmat;
+};
+
+std::shared_ptr<const PremixSkel> make_skeleton(Ctx* ctx, const MpoHost& W, int site, bool left) {
+  const MpoCut& mc = W.cut[left ? site + 1 : site];
+  const MpoCut& sc = W.cut[left ? site : site + 1];
+  auto sk = std::make_shared<PremixSkel>();
+  sk->ch.resize(mc.size());
   // per middle channel, per pattern: list of (source channel, coefficient)
   std::vector<std::map<int, std::vector<std::pair<int, double>>>> per(mc.size());
   for (const auto& e : W.W[site]) {
@@ -67,77 +82,140 @@ SideOps build_ops(Contractor& C, const Env& E, const MpoHost& W, int site, bool 
   std::map<MixGroupKey, std::vector<MixRow>> mix;
   for (int v = 0; v < mc.size(); ++v) {
     for (auto& kv : per[v]) {
-      ops.ch[v].pat.push_back(kv.first);
-      OpRef r;
+      sk->ch[v].pat.push_back(kv.first);
+      SkelRef r;
       if (kv.second.size() == 1) {
         int w = kv.second[0].first;
-        r.src = &E.b;
         r.grp = sc.cls_of[w];
         r.idx = w - sc.cls_start[r.grp];
         r.coef = kv.second[0].second;
       } else {
-        r.src = nullptr;  // filled below
+        r.mix = true;  // grp / idx filled below
         mix[{kv.first, mc.cls_of[v]}].push_back({v, kv.second});
       }
-      ops.ch[v].ref.push_back(r);
+      sk->ch[v].ref.push_back(r);
     }
   }
-  if (mix.empty()) return ops;
-  // premix layout: one group per (pattern, middle class)
-  std::vector<std::pair<Charge, int>> groups;
-  std::vector<int> src_cls;
+  if (mix.empty()) return sk;
+  // premix layout: one group per (pattern, middle class), coefficient matrices dense over the
+  // used source range
+  std::vector<cplx> wmat;
+  int g = 0;
   for (auto& kv : mix) {
     int w0 = kv.second[0].src[0].first;
     int cw = sc.cls_of[w0];
-    for (auto& row : kv.second)
-      for (auto& s : row.src)
-        TDMPS_REQUIRE(sc.cls_of[s.first] == cw, TDMPS_ERR_NUMERIC, "internal: premix sources differ in charge");
-    groups.push_back({sc.cls_q[cw], (int)kv.second.size()});
-    src_cls.push_back(cw);
-  }
-  ops.mix.reset(new Blocks());
-  ops.mix->layout(E.b.bra, E.b.ket, groups);
-  ops.mix->data = DevBuf(ops.mix->size * sizeof(cplx));
-  // coefficient matrices (dense over the used source range) and GEMMs per ket sector
-  std::vector<cplx> wmat;
-  struct Pending {
-    int g, cw, wlo, ncol;
-    size_t off;
-  };
-  std::vector<Pending> pend;
-  int g = 0;
-  for (auto& kv : mix) {
-    int cw = src_cls[g];
     int lo = 1 << 30, hi = -1;
     for (auto& row : kv.second)
       for (auto& s : row.src) {
+        TDMPS_REQUIRE(sc.cls_of[s.first] == cw, TDMPS_ERR_NUMERIC, "internal: premix sources differ in charge");
         lo = std::min(lo, s.first);
         hi = std::max(hi, s.first);
       }
+    sk->groups.push_back({sc.cls_q[cw], (int)kv.second.size()});
     int ncol = hi - lo + 1;
     size_t off = wmat.size();
     wmat.resize(off + (size_t)kv.second.size() * ncol, cplx{0, 0});
     for (size_t r = 0; r < kv.second.size(); ++r) {
       for (auto& s : kv.second[r].src) wmat[off + r * ncol + (s.first - lo)].x += s.second;
-      int v = kv.second[r].v;
-      for (size_t k = 0; k < ops.ch[v].pat.size(); ++k)
-        if (ops.ch[v].pat[k] == kv.first.pat) {
-          ops.ch[v].ref[k].src = ops.mix.get();
-          ops.ch[v].ref[k].grp = g;
-          ops.ch[v].ref[k].idx = (int)r;
-          ops.ch[v].ref[k].coef = 1.0;
+      SkelChan& ch = sk->ch[kv.second[r].v];
+      for (size_t k = 0; k < ch.pat.size(); ++k)
+        if (ch.pat[k] == kv.first.pat) {
+          ch.ref[k].grp = g;
+          ch.ref[k].idx = (int)r;
+          ch.ref[k].coef = 1.0;
         }
     }
-    pend.push_back({g, cw, lo - sc.cls_start[cw], ncol, off});
+    sk->pend.push_back({g, cw, lo - sc.cls_start[cw], ncol, off});
     ++g;
   }
-  ops.wmat.reset(new DevBuf(std::max<size_t>(wmat.size(), 1) * sizeof(cplx)));
-  dev_h2d(ops.wmat->p, wmat.data(), wmat.size() * sizeof(cplx), C.ctx->stream);
-  const cplx* dw = ops.wmat->c();
+  sk->wmat = std::make_shared<DevBuf>(wmat.size() * sizeof(cplx));
+  dev_h2d(sk->wmat->p, wmat.data(), wmat.size() * sizeof(cplx), ctx->stream);
+  return sk;
+}
+
+struct SkelKey {
+  void* stream;
+  uint64_t version;
+  int site;
+  bool left;
+  bool operator<(const SkelKey& o) const {
+    return std::tie(stream, version, site, left) < std::tie(o.stream, o.version, o.site, o.left);
+  }
+};
+struct SkelEntry {
+  std::shared_ptr<const PremixSkel> sk;
+  size_t bytes;
+  uint64_t stamp;
+};
+std::mutex g_skel_mu;
+std::map<SkelKey, SkelEntry> g_skel;
+uint64_t g_skel_clock = 0;
+size_t g_skel_bytes = 0;
+constexpr size_t SKEL_MAX_ENTRIES = 1024;
+constexpr size_t SKEL_MAX_BYTES = (size_t)2 << 30;
+
+// The coefficient buffer is uploaded on, and only read on, the stream of the key, so the
+// caching allocator's stream order covers its reuse after eviction.
+std::shared_ptr<const PremixSkel> premix_skeleton(Ctx* ctx, const MpoHost& W, int site, bool left) {
+  const SkelKey key{ctx->stream, W.version, site, left};
+  std::lock_guard<std::mutex> lk(g_skel_mu);
+  auto it = g_skel.find(key);
+  if (it != g_skel.end()) {
+    it->second.stamp = ++g_skel_clock;
+    return it->second.sk;
+  }
+  auto sk = make_skeleton(ctx, W, site, left);
+  const size_t bytes = sk->wmat ? sk->wmat->bytes : 0;
+  while (!g_skel.empty() && (g_skel.size() >= SKEL_MAX_ENTRIES || g_skel_bytes + bytes > SKEL_MAX_BYTES)) {
+    auto oldest = g_skel.begin();
+    for (auto e = g_skel.begin(); e != g_skel.end(); ++e)
+      if (e->second.stamp < oldest->second.stamp) oldest = e;
+    g_skel_bytes -= oldest->second.bytes;
+    g_skel.erase(oldest);
+  }
+  g_skel.emplace(key, SkelEntry{sk, bytes, ++g_skel_clock});
+  g_skel_bytes += bytes;
+  return sk;
+}
+
+// With ext != nullptr the premix products are appended to *ext (run by the caller) instead
+// of being run here.
+SideOps build_ops(Contractor& C, const Env& E, const MpoHost& W, int site, bool left, GemmPlan* ext = nullptr) {
+  const double t0 = wall_seconds();
+  struct Acc {
+    Contractor& C;
+    double t0;
+    ~Acc() { C.t_mix += wall_seconds() - t0; }
+  } acc_{C, t0};
+  TDMPS_REQUIRE(E.cut == (left ? site : site + 1), TDMPS_ERR_ARG, "internal: premix environment cut");
+  const auto sk = premix_skeleton(C.ctx, W, site, left);
+  SideOps ops;
+  ops.cut = left ? site + 1 : site;
+  ops.env = &E;
+  if (!sk->groups.empty()) {
+    ops.mix.reset(new Blocks());
+    ops.mix->layout(E.b.bra, E.b.ket, sk->groups);
+    ops.mix->data = DevBuf(ops.mix->size * sizeof(cplx));
+    ops.wmat = sk->wmat;
+  }
+  ops.ch.resize(sk->ch.size());
+  for (size_t v = 0; v < sk->ch.size(); ++v) {
+    const SkelChan& sc = sk->ch[v];
+    ChanOps& co = ops.ch[v];
+    co.pat = sc.pat;
+    co.ref.resize(sc.ref.size());
+    for (size_t k = 0; k < sc.ref.size(); ++k) {
+      const SkelRef& r = sc.ref[k];
+      co.ref[k] = OpRef{r.mix ? ops.mix.get() : &E.b, r.grp, r.idx, r.coef};
+    }
+  }
+  if (sk->groups.empty()) return ops;
+  // one real-coefficient GEMM over the source channels per group and ket sector
+  const cplx* dw = sk->wmat->c();
   GemmPlan local;
   GemmPlan& plan = ext ? *ext : local;
   const Blocks& eb = E.b;
-  for (auto& p : pend) {
+  for (const auto& p : sk->pend) {
     const StackGroup& sg = ops.mix->grp[p.g];
     for (int ks = 0; ks < eb.ket.nsec(); ++ks) {
       if (sg.off[ks] < 0) continue;
@@ -151,6 +229,7 @@ SideOps build_ops(Contractor& C, const Env& E, const MpoHost& W, int site, bool 
   }
   if (!ext) {
     plan.run(C.ctx, TDMPS_FP64, C.batched);
+    if (C.ctx->phase_sync) dev_sync(C.ctx->stream);
     C.mix_flops += plan.flops;
   }
   return ops;
@@ -237,10 +316,10 @@ void env_left_plan(const SideOps& ops, const cplx* bra_site, const SiteLayout& b
   struct TKey {
     int r, s, sig, tk;
   };
+  // the second stage below visits the (r, tk, s, sig) keys in the order they are created here
   std::vector<TKey> tkeys;
   std::vector<int64_t> toff;
   int64_t tsize = 0;
-  std::map<std::tuple<int, int, int, int>, int> tindex;
   for (int r = 0; r < (int)runs.size(); ++r) {
     int v0 = runs[r].v0;
     int g = mc.cls_of[v0];
@@ -251,7 +330,6 @@ void env_left_plan(const SideOps& ops, const cplx* bra_site, const SiteLayout& b
       for (int s = 0; s < bra_l.nsec(); ++s)
         for (int sig = 0; sig < 4; ++sig) {
           if (bl.rs[s][sig] != tb) continue;
-          tindex[{r, s, sig, tk}] = (int)tkeys.size();
           tkeys.push_back({r, s, sig, tk});
           toff.push_back(tsize);
           tsize += (int64_t)runs[r].n * bra_l.dim[s] * ket_r.dim[tk];
@@ -286,6 +364,7 @@ void env_left_plan(const SideOps& ops, const cplx* bra_site, const SiteLayout& b
     tnonzero[t] = started;
   }
   // L'_v[t, t'] = sum_{s, sig} conj(C[s, sig, t])^T T_v[s, sig, t']
+  size_t cursor = 0;
   for (int r = 0; r < (int)runs.size(); ++r) {
     int v0 = runs[r].v0;
     int g = mc.cls_of[v0];
@@ -299,8 +378,11 @@ void env_left_plan(const SideOps& ops, const cplx* bra_site, const SiteLayout& b
       for (int s = 0; s < bra_l.nsec(); ++s)
         for (int sig = 0; sig < 4; ++sig) {
           if (bl.rs[s][sig] != tb) continue;
-          auto it = tindex.find({r, s, sig, tk});
-          if (it == tindex.end() || !tnonzero[it->second]) continue;
+          const size_t t = cursor++;
+          TDMPS_REQUIRE(t < tkeys.size() && tkeys[t].r == r && tkeys[t].s == s && tkeys[t].sig == sig &&
+                            tkeys[t].tk == tk,
+                        TDMPS_ERR_NUMERIC, "internal: T key order");
+          if (!tnonzero[t]) continue;
           int Ds = bra_l.dim[s];
           if (!started) {
             p2.begin_task(out.b.stack(g, tk) + (int64_t)j0 * Dt * Dtk, (int64_t)Dt * Dtk, Dtk, Dt, Dtk, runs[r].n,
@@ -308,8 +390,7 @@ void env_left_plan(const SideOps& ops, const cplx* bra_site, const SiteLayout& b
             started = true;
           }
           const cplx* A = bra_site + bl.panel_off[s] + bl.col[s][sig];
-          p2.add_seg(A, 0, 0, bl.width[s], OP_C, T.c() + toff[it->second], (int64_t)Ds * Dtk, 0, Dtk, OP_N, Ds, 1,
-                     ONE);
+          p2.add_seg(A, 0, 0, bl.width[s], OP_C, T.c() + toff[t], (int64_t)Ds * Dtk, 0, Dtk, OP_N, Ds, 1, ONE);
         }
     }
   }
@@ -326,6 +407,7 @@ Env env_left_update(Contractor& C, const SideOps& ops, const Mps*, const cplx* b
   const double tb = wall_seconds();
   p1.run(C.ctx, C.precision, C.batched);
   p2.run(C.ctx, C.precision, C.batched);
+  if (C.ctx->phase_sync) dev_sync(C.ctx->stream);
   C.t_plan += (tb - t0) + p1.host_s + p2.host_s;
   C.env_flops += p1.flops + p2.flops;
   C.t_env += wall_seconds() - t0;
@@ -348,10 +430,10 @@ Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, co
   struct TKey {
     int r, sk, sig, tb;
   };
+  // the second stage below visits the (r, sk, sig) keys in the order they are created here
   std::vector<TKey> tkeys;
   std::vector<int64_t> toff;
   int64_t tsize = 0;
-  std::map<std::tuple<int, int, int, int>, int> tindex;
   for (int r = 0; r < (int)runs.size(); ++r) {
     int g = mc.cls_of[runs[r].v0];
     const StackGroup& og = out.b.grp[g];
@@ -361,7 +443,6 @@ Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, co
       for (int sig = 0; sig < 4; ++sig) {
         int tb = bl.rs[sb][sig];
         if (tb < 0) continue;
-        tindex[{r, sk, sig, tb}] = (int)tkeys.size();
         tkeys.push_back({r, sk, sig, tb});
         toff.push_back(tsize);
         tsize += (int64_t)runs[r].n * ket_l.dim[sk] * bra_r.dim[tb];
@@ -401,6 +482,7 @@ Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, co
   const double te1 = wall_seconds();
   // R'_v[s, s'] = sum_{sig, t} conj(C[s, sig, t]) T_v[s', sig, t]^T
   GemmPlan p2;
+  size_t cursor = 0;
   for (int r = 0; r < (int)runs.size(); ++r) {
     int v0 = runs[r].v0;
     int g = mc.cls_of[v0];
@@ -414,20 +496,24 @@ Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, co
       for (int sig = 0; sig < 4; ++sig) {
         int tb = bl.rs[sb][sig];
         if (tb < 0) continue;
-        auto it = tindex.find({r, sk, sig, tb});
-        if (it == tindex.end() || !tnonzero[it->second]) continue;
+        const size_t t = cursor++;
+        TDMPS_REQUIRE(t < tkeys.size() && tkeys[t].r == r && tkeys[t].sk == sk && tkeys[t].sig == sig &&
+                          tkeys[t].tb == tb,
+                      TDMPS_ERR_NUMERIC, "internal: T key order");
+        if (!tnonzero[t]) continue;
         int Dt = bra_r.dim[tb];
         if (!started) {
           p2.begin_task(out.b.stack(g, sk) + (int64_t)j0 * Ds * Dsk, (int64_t)Ds * Dsk, Dsk, Ds, Dsk, runs[r].n, true);
           started = true;
         }
         const cplx* A = bra_site + bl.panel_off[sb] + bl.col[sb][sig];
-        p2.add_seg(A, 0, 0, bl.width[sb], OP_J, T.c() + toff[it->second], (int64_t)Dsk * Dt, 0, Dt, OP_T, Dt, 1, ONE);
+        p2.add_seg(A, 0, 0, bl.width[sb], OP_J, T.c() + toff[t], (int64_t)Dsk * Dt, 0, Dt, OP_T, Dt, 1, ONE);
       }
     }
   }
   const double tb2 = wall_seconds();
   p2.run(C.ctx, C.precision, C.batched);
+  if (C.ctx->phase_sync) dev_sync(C.ctx->stream);
   C.t_plan += (tb1 - t0) + (tb2 - te1) + p1.host_s + p2.host_s;
   C.env_flops += p1.flops + p2.flops;
   C.t_env += wall_seconds() - t0;
@@ -745,11 +831,13 @@ std::vector<cplx> sandwich_many(Contractor& C, const MpoHost& O, const std::vect
       }
       const double tr = wall_seconds();
       P0.run(C.ctx, TDMPS_FP64, C.batched);
+      if (C.ctx->phase_sync) dev_sync(C.ctx->stream);
       C.mix_flops += P0.flops;
       const double te = wall_seconds();
       C.t_mix += te - tr;
       P1.run(C.ctx, C.precision, C.batched);
       P2.run(C.ctx, C.precision, C.batched);
+      if (C.ctx->phase_sync) dev_sync(C.ctx->stream);
       C.t_plan += (tr - tp) + P0.host_s + P1.host_s + P2.host_s;
       C.env_flops += P1.flops + P2.flops;
       C.t_env += wall_seconds() - te;

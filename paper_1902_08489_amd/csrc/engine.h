@@ -210,7 +210,7 @@ struct SideOps {
   const Env* env = nullptr;
   std::vector<ChanOps> ch;
   std::unique_ptr<Blocks> mix;
-  std::unique_ptr<DevBuf> wmat;  // premix coefficients (device), alive until the premix plan ran
+  std::shared_ptr<DevBuf> wmat;  // premix coefficients (device), alive until the premix plan ran
 };
 
 // ---------------------------------------------------------------- GEMM plans

@@ -90,7 +90,15 @@ struct Cursor {
 // prefetch of the next stage.
 typedef const __attribute__((address_space(1))) double* gptr;
 
-template <int BM, int BN, int BK>
+// Element -> thread mapping of the B stage, whatever the operand's storage: BMAP_N puts
+// adjacent threads on adjacent columns, BMAP_K on adjacent k.  The LDS layout decides, not
+// the global one: FP64 / FP32 store B' row-major, where threads adjacent along k would
+// write rows 2 apart on the same banks (BMAP_N: the final H_eff stage, whose B is
+// transposed, 16.8 -> 12.8 ms at L = 24, D = 1024); the bf16 planes store B'^T, where
+// adjacent k are adjacent words (BMAP_K: 39.9 -> 36.8 ms for the whole H_eff).
+enum { BMAP_N = 1, BMAP_K = 2 };
+
+template <int BM, int BN, int BK, int BMAP>
 struct Stage {
   // per-thread prefetch registers: ceil(BM*BK/256) A elements and ceil(BK*BN/256) B elements,
   // raw as loaded (conjugation and the segment scale are applied when they are written to LDS,
@@ -128,7 +136,7 @@ struct Stage {
     for (int q = 0; q < NB; ++q) {
       const int e = tid + q * 256;
       int kk, cc;
-      if (!c.tB) {
+      if (BMAP == BMAP_N) {
         kk = e / BN;
         cc = e - kk * BN;
       } else {
@@ -156,6 +164,7 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 //   PBF3 : bf16 split x = hi + lo of the FP32-rounded operand, products hi*hi + hi*lo + lo*hi
 //          on the 16x16x32 bf16 MFMA with FP32 accumulate (LDS: realified hi / lo planes)
 enum { P64 = 0, P32 = 1, PBF3 = 2 };
+
 
 template <int BM, int BN, int PREC>
 struct Smem;
@@ -189,12 +198,19 @@ __device__ __forceinline__ void split_bf16(double x, __bf16& h, __bf16& l) {
   l = (__bf16)(f - (float)h);
 }
 
+// two bf16 as one 32-bit LDS word (the first at the lower address)
+__device__ __forceinline__ uint32_t pack_bf16(__bf16 lo, __bf16 hi) {
+  return (uint32_t)__builtin_bit_cast(unsigned short, lo) | ((uint32_t)__builtin_bit_cast(unsigned short, hi) << 16);
+}
+
 template <int BM, int BN, int PREC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void gemm_kernel(const GemmTask* __restrict__ tasks,
                                                    const GemmSeg* __restrict__ segs,
                                                    const int32_t* __restrict__ tile_task, int64_t total_tiles,
                                                    int64_t tile_offset) {
   constexpr int BK = PREC == P64 ? 8 : 16;  // complex k per LDS stage (FP64: fewer live registers)
+  constexpr int BMAP = PREC == PBF3 ? BMAP_K : BMAP_N;
+  typedef Stage<BM, BN, BK, BMAP> St;
   constexpr int WM = BM / 2;                 // complex rows per wave
   constexpr int WN = BN / 2;                 // complex columns per wave
   constexpr int TM = WM / 16;                // 16x16 MFMA tiles along m
@@ -228,7 +244,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-  Stage<BM, BN, BK> st;
+  St st;
   Cursor cur;
   cur.segs = segs;
   cur.s = T.seg0;
@@ -239,11 +255,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     // registers -> LDS in the precision's layout
     {
       const bool transA = cur.tA;
-      const bool transB = cur.tB;
 #pragma unroll
-      for (int q = 0; q < Stage<BM, BN, BK>::NA; ++q) {
+      for (int q = 0; q < St::NA; ++q) {
         const int e = tid + q * 256;
-        if (!Stage<BM, BN, BK>::FULLA && e >= BM * BK) continue;
+        if (!St::FULLA && e >= BM * BK) continue;
         int rr, kk;
         if (!transA) {
           rr = e / BK;
@@ -260,16 +275,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         } else if constexpr (PREC == P32) {
           *(float2*)&sm.A[rr][2 * kk] = make_float2((float)v.x, (float)v.y);
         } else {
-          split_bf16(v.x, sm.Ah[rr][2 * kk], sm.Al[rr][2 * kk]);
-          split_bf16(v.y, sm.Ah[rr][2 * kk + 1], sm.Al[rr][2 * kk + 1]);
+          __bf16 xh, xl, yh, yl;
+          split_bf16(v.x, xh, xl);
+          split_bf16(v.y, yh, yl);
+          *(uint32_t*)&sm.Ah[rr][2 * kk] = pack_bf16(xh, yh);
+          *(uint32_t*)&sm.Al[rr][2 * kk] = pack_bf16(xl, yl);
         }
       }
 #pragma unroll
-      for (int q = 0; q < Stage<BM, BN, BK>::NB; ++q) {
+      for (int q = 0; q < St::NB; ++q) {
         const int e = tid + q * 256;
-        if (!Stage<BM, BN, BK>::FULLB && e >= BK * BN) continue;
+        if (!St::FULLB && e >= BK * BN) continue;
         int kk, cc;
-        if (!transB) {
+        if (BMAP == BMAP_N) {
           kk = e / BN;
           cc = e - kk * BN;
         } else {
@@ -291,14 +309,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
           split_bf16(v.x, rh, rl);
           split_bf16(v.y, ih, il);
           split_bf16(-v.y, nh, nl);
-          sm.Bh[2 * cc][2 * kk] = rh;
-          sm.Bl[2 * cc][2 * kk] = rl;
-          sm.Bh[2 * cc + 1][2 * kk] = ih;
-          sm.Bl[2 * cc + 1][2 * kk] = il;
-          sm.Bh[2 * cc][2 * kk + 1] = nh;
-          sm.Bl[2 * cc][2 * kk + 1] = nl;
-          sm.Bh[2 * cc + 1][2 * kk + 1] = rh;
-          sm.Bl[2 * cc + 1][2 * kk + 1] = rl;
+          *(uint32_t*)&sm.Bh[2 * cc][2 * kk] = pack_bf16(rh, nh);
+          *(uint32_t*)&sm.Bl[2 * cc][2 * kk] = pack_bf16(rl, nl);
+          *(uint32_t*)&sm.Bh[2 * cc + 1][2 * kk] = pack_bf16(ih, rh);
+          *(uint32_t*)&sm.Bl[2 * cc + 1][2 * kk] = pack_bf16(il, rl);
         }
       }
     }

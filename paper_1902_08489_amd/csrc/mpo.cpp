@@ -21,6 +21,7 @@
 #include "mpo.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <map>
 #include <tuple>
@@ -406,7 +407,12 @@ void mpo_set_one_body(MpoHost& m, const double* h) {
   for (int p = 0; p < L; ++p)
     for (size_t e = 0; e < m.W[p].size(); ++e) m.W[p][e].c = m.c_fixed[p][e];
   for (auto& r : m.onebody) m.W[r.site][r.entry].c += h[r.p * L + r.q] * r.factor;
-  m.version++;
+  m.version = next_mpo_version();
+}
+
+uint64_t next_mpo_version() {
+  static std::atomic<uint64_t> counter{0};
+  return ++counter;
 }
 
 // Dense operator by contracting the channels left to right (tiny L only).

@@ -37,6 +37,8 @@ struct OneBodyRef {
   double factor;
 };
 
+uint64_t next_mpo_version();
+
 struct MpoHost {
   int L = 0;
   std::vector<MpoCut> cut;                   // L+1 cuts (cut i is left of site i)
@@ -44,7 +46,9 @@ struct MpoHost {
   std::vector<std::vector<double>> c_fixed;  // part of each coefficient not from h
   std::vector<OneBodyRef> onebody;           // linear dependence of coefficients on h
   std::vector<double> h;
-  uint64_t version = 0;                      // bumped by set_one_body
+  // Identifies the coefficients: a process-wide counter gives every new operator and every
+  // set_one_body a fresh value, and copies keep it while their coefficients are equal.
+  uint64_t version = next_mpo_version();
 };
 
 MpoHost build_mpo(int L, const double* h, const double* eri, double e0, bool two_body);

@@ -2,6 +2,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "engine.h"
 
@@ -495,7 +497,7 @@ Mps* mps_annihilate(Ctx* ctx, const Mps* psi, int j, int sigma) {
   return m;
 }
 
-MpoHost identity_mpo(int L) {
+static MpoHost build_identity_mpo(int L) {
   MpoHost M;
   M.L = L;
   M.cut.resize(L + 1);
@@ -517,6 +519,17 @@ MpoHost identity_mpo(int L) {
     }
   M.h.assign((size_t)L * L, 0.0);
   return M;
+}
+
+// One operator per length, so that its version (and the premix structures cached under it)
+// stays the same from call to call.
+MpoHost identity_mpo(int L) {
+  static std::mutex mu;
+  static std::map<int, MpoHost> made;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = made.find(L);
+  if (it == made.end()) it = made.emplace(L, build_identity_mpo(L)).first;
+  return it->second;
 }
 
 void scale_mps(Ctx* ctx, Mps* m, cplx alpha) {
