@@ -229,23 +229,36 @@ static KrylovBasis krylov_basis(Contractor& C, const MpoHost* H, const Mps* psi,
     for (int j = 0; j < n; ++j) b.push_back(phi[j].get());
     return b;
   };
+  // Column k of H: <phi_j|H|phi_k> for all j <= k in one batched sweep, except j = k - 1,
+  // which the fit that produced phi_k already gave exactly (FitOut::h_out_psi)
+  auto column = [&](int k, bool have_prev) {
+    std::vector<const Mps*> b;
+    std::vector<int> idx;
+    for (int j = 0; j <= k; ++j)
+      if (!(have_prev && j == k - 1)) {
+        b.push_back(phi[j].get());
+        idx.push_back(j);
+      }
+    const std::vector<cplx> hk = sandwich_many(C, *H, b, phi[k].get());
+    for (size_t q = 0; q < idx.size(); ++q) {
+      const int j = idx[q];
+      Hm[j * m + k] = z(hk[q]);
+      Hm[k * m + j] = std::conj(Hm[j * m + k]);
+    }
+  };
   int meff = m;
   for (int k = 0; k < m - 1; ++k) {
-    // H_jk = <phi_j|H|phi_k> for all j <= k in one batched sweep
-    const std::vector<cplx> hk = sandwich_many(C, *H, bras(k + 1), phi[k].get());
+    column(k, k > 0);
     double proj = 0;
-    for (int j = 0; j <= k; ++j) {
-      Hm[j * m + k] = z(hk[j]);
-      Hm[k * m + j] = std::conj(Hm[j * m + k]);
-      proj += std::norm(Hm[j * m + k]) / N[j * m + j].real();
-    }
+    for (int j = 0; j <= k; ++j) proj += std::norm(Hm[j * m + k]) / N[j * m + j].real();
     std::vector<FitTerm> terms;
     if (orthogonal)
       for (int j = 0; j <= k; ++j) {
         zd b = -Hm[j * m + k] / N[j * m + j];
         terms.push_back({cplx{b.real(), b.imag()}, phi[j].get()});
       }
-    std::unique_ptr<Mps> nxt(fit(C, H, cplx{1, 0}, phi[k].get(), terms, prm, nullptr));
+    FitOut fo;
+    std::unique_ptr<Mps> nxt(fit(C, H, cplx{1, 0}, phi[k].get(), terms, prm, &fo));
     if (progress)
       std::fprintf(stderr, "krylov: vector %d of %d after %.1f s\n", k + 1, m - 1, wall_seconds() - t_start);
     double nn = overlap(C, nxt.get(), nxt.get()).x;
@@ -257,19 +270,16 @@ static KrylovBasis krylov_basis(Contractor& C, const MpoHost* H, const Mps* psi,
     TDMPS_REQUIRE(nn > 0, TDMPS_ERR_SINGULAR, "Krylov vector vanished");
     scale_mps(C.ctx, nxt.get(), cplx{1.0 / std::sqrt(nn), 0.0});
     phi.push_back(std::move(nxt));
+    // <phi_{k+1}|H|phi_k> of the normalised vector
+    Hm[(k + 1) * m + k] = z(fo.h_out_psi) / std::sqrt(nn);
+    Hm[k * m + k + 1] = std::conj(Hm[(k + 1) * m + k]);
     const std::vector<cplx> nk = sandwich_many(C, I, bras(k + 2), phi[k + 1].get());
     for (int j = 0; j <= k + 1; ++j) {
       N[j * m + k + 1] = z(nk[j]);
       N[(k + 1) * m + j] = std::conj(N[j * m + k + 1]);
     }
   }
-  if (meff == m) {
-    const std::vector<cplx> hl = sandwich_many(C, *H, bras(m), phi[m - 1].get());
-    for (int j = 0; j < m; ++j) {
-      Hm[j * m + m - 1] = z(hl[j]);
-      Hm[(m - 1) * m + j] = std::conj(Hm[j * m + m - 1]);
-    }
-  }
+  if (meff == m) column(m - 1, true);
   K.meff = meff;
   return K;
 }

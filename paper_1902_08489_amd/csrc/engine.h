@@ -340,6 +340,11 @@ struct FitTerm {
 struct FitOut {
   int sweeps = 0;
   double disc_max = 0, disc_sum = 0, norm2 = 0;
+  // <out|H|psi> of the returned state (H term only, without alpha), read off the last local
+  // problem of the last sweep: at bond (0, 1) the right environment is built from the final
+  // sites, so the local projection of H psi dotted with the final two-site tensor is exact.
+  // Set when H is given.
+  cplx h_out_psi{0, 0};
 };
 // out ~ alpha * H psi + sum_j beta_j phi_j  (H may be null: compression only)
 Mps* fit(Contractor& C, const MpoHost* H, cplx alpha, const Mps* psi, const std::vector<FitTerm>& terms,

@@ -79,6 +79,9 @@ Mps* fit(Contractor& C, const MpoHost* H, cplx alpha, const Mps* psi, const std:
         bl.build(Cm->bond[i], Cm->bond[i + 2]);
         DevBuf theta(std::max<int64_t>(bl.size, 1) * sizeof(cplx));
         std::vector<std::unique_ptr<SideOps>> lkeep(T.size()), rkeep(T.size());
+        // at the last local problem of a sweep, the H term's output alone (for <out|H|psi>)
+        const bool last_bond = H && dir == 1 && i == 0;
+        std::vector<cplx> h_local;
         bool first_term = true;
         for (size_t k = 0; k < T.size(); ++k) {
           Term& t = T[k];
@@ -93,8 +96,31 @@ Mps* fit(Contractor& C, const MpoHost* H, cplx alpha, const Mps* psi, const std:
                      Cm->bond[i], Cm->bond[i + 2], t.coef, !first_term, t.op == H ? &alg : nullptr);
           C.heff_alg_flops += alg;
           first_term = false;
+          if (last_bond && k == 0) {
+            h_local.resize(bl.size);
+            if (bl.size) dev_d2h(h_local.data(), theta.c(), bl.size * sizeof(cplx), C.ctx->stream);
+          }
         }
         TruncResult tr = split_theta(C, theta.c(), bl, Cm.get(), i, prm.Dmax, prm.svd_cutoff, dir == 0);
+        if (last_bond) {
+          // bonds 0 and 2 of the result are unchanged by the split, so the final two-site
+          // tensor has the layout of theta
+          std::vector<cplx> fin(bl.size);
+          if (bl.size) {
+            DevBuf tf(bl.size * sizeof(cplx));
+            form_theta(C, Cm.get(), 0, tf.c(), bl);
+            dev_d2h(fin.data(), tf.c(), bl.size * sizeof(cplx), C.ctx->stream);
+          }
+          double re = 0, im = 0;
+          for (int64_t x = 0; x < bl.size; ++x) {
+            re += fin[x].x * h_local[x].x + fin[x].y * h_local[x].y;
+            im += fin[x].x * h_local[x].y - fin[x].y * h_local[x].x;
+          }
+          // the H term carried alpha
+          const double a2 = alpha.x * alpha.x + alpha.y * alpha.y;
+          out.h_out_psi = a2 > 0 ? cplx{(re * alpha.x + im * alpha.y) / a2, (im * alpha.x - re * alpha.y) / a2}
+                                 : cplx{0, 0};
+        }
         out.disc_max = std::max(out.disc_max, tr.discarded);
         out.disc_sum += tr.discarded;
         last_norm = tr.norm2;
