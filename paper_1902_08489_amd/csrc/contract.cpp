@@ -147,8 +147,11 @@ struct SkelEntry {
   size_t bytes;
   uint64_t stamp;
 };
-std::mutex g_skel_mu;
-std::map<SkelKey, SkelEntry> g_skel;
+// Held through pointers that are never deleted: entries own device buffers, and a
+// destructor at process exit would free them into the allocator's tables (another
+// translation unit), which may already have been destroyed.
+std::mutex& g_skel_mu = *new std::mutex;
+std::map<SkelKey, SkelEntry>& g_skel = *new std::map<SkelKey, SkelEntry>;
 uint64_t g_skel_clock = 0;
 size_t g_skel_bytes = 0;
 constexpr size_t SKEL_MAX_ENTRIES = 1024;

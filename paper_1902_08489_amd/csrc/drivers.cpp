@@ -273,10 +273,19 @@ static KrylovBasis krylov_basis(Contractor& C, const MpoHost* H, const Mps* psi,
     // <phi_{k+1}|H|phi_k> of the normalised vector
     Hm[(k + 1) * m + k] = z(fo.h_out_psi) / std::sqrt(nn);
     Hm[k * m + k + 1] = std::conj(Hm[(k + 1) * m + k]);
-    const std::vector<cplx> nk = sandwich_many(C, I, bras(k + 2), phi[k + 1].get());
-    for (int j = 0; j <= k + 1; ++j) {
-      N[j * m + k + 1] = z(nk[j]);
-      N[(k + 1) * m + j] = std::conj(N[j * m + k + 1]);
+    if (orthogonal && fo.term_overlaps.size() == (size_t)(k + 1)) {
+      // the fit's terms were phi_0 .. phi_k: their overlaps with the result are exact
+      for (int j = 0; j <= k; ++j) {
+        N[(k + 1) * m + j] = z(fo.term_overlaps[j]) / std::sqrt(nn);
+        N[j * m + k + 1] = std::conj(N[(k + 1) * m + j]);
+      }
+      N[(k + 1) * m + k + 1] = z(overlap(C, phi[k + 1].get(), phi[k + 1].get()));
+    } else {
+      const std::vector<cplx> nk = sandwich_many(C, I, bras(k + 2), phi[k + 1].get());
+      for (int j = 0; j <= k + 1; ++j) {
+        N[j * m + k + 1] = z(nk[j]);
+        N[(k + 1) * m + j] = std::conj(N[j * m + k + 1]);
+      }
     }
   }
   if (meff == m) column(m - 1, true);

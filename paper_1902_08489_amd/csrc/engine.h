@@ -345,6 +345,8 @@ struct FitOut {
   // sites, so the local projection of H psi dotted with the final two-site tensor is exact.
   // Set when H is given.
   cplx h_out_psi{0, 0};
+  // <out|phi_j> for every fit term, read off the same local problem.
+  std::vector<cplx> term_overlaps;
 };
 // out ~ alpha * H psi + sum_j beta_j phi_j  (H may be null: compression only)
 Mps* fit(Contractor& C, const MpoHost* H, cplx alpha, const Mps* psi, const std::vector<FitTerm>& terms,

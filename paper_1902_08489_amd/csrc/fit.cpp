@@ -79,9 +79,10 @@ Mps* fit(Contractor& C, const MpoHost* H, cplx alpha, const Mps* psi, const std:
         bl.build(Cm->bond[i], Cm->bond[i + 2]);
         DevBuf theta(std::max<int64_t>(bl.size, 1) * sizeof(cplx));
         std::vector<std::unique_ptr<SideOps>> lkeep(T.size()), rkeep(T.size());
-        // at the last local problem of a sweep, the H term's output alone (for <out|H|psi>)
-        const bool last_bond = H && dir == 1 && i == 0;
-        std::vector<cplx> h_local;
+        // at the last local problem of a sweep, every term's output alone (for <out|H|psi> and
+        // <out|phi_j>); the two-site tensors there are tiny (bond 0 has dimension one)
+        const bool last_bond = dir == 1 && i == 0;
+        std::vector<std::vector<cplx>> local(last_bond ? T.size() : 0);
         bool first_term = true;
         for (size_t k = 0; k < T.size(); ++k) {
           Term& t = T[k];
@@ -91,15 +92,18 @@ Mps* fit(Contractor& C, const MpoHost* H, cplx alpha, const Mps* psi, const std:
           form_theta(C, t.ket, i, tin.c(), kl);
           lkeep[k] = std::make_unique<SideOps>(premix_left(C, *t.Lenv[i], *t.op, i));
           rkeep[k] = std::make_unique<SideOps>(premix_right(C, *t.Renv[i + 2], *t.op, i + 1));
+          if (last_bond && bl.size) {
+            DevBuf part(bl.size * sizeof(cplx));
+            heff_apply(C, *lkeep[k], *rkeep[k], tin.c(), kl, t.ket->bond[i], t.ket->bond[i + 2], part.c(), bl,
+                       Cm->bond[i], Cm->bond[i + 2], cplx{1, 0}, false, nullptr);
+            local[k].resize(bl.size);
+            dev_d2h(local[k].data(), part.c(), bl.size * sizeof(cplx), C.ctx->stream);
+          }
           double alg = 0;
           heff_apply(C, *lkeep[k], *rkeep[k], tin.c(), kl, t.ket->bond[i], t.ket->bond[i + 2], theta.c(), bl,
                      Cm->bond[i], Cm->bond[i + 2], t.coef, !first_term, t.op == H ? &alg : nullptr);
           C.heff_alg_flops += alg;
           first_term = false;
-          if (last_bond && k == 0) {
-            h_local.resize(bl.size);
-            if (bl.size) dev_d2h(h_local.data(), theta.c(), bl.size * sizeof(cplx), C.ctx->stream);
-          }
         }
         TruncResult tr = split_theta(C, theta.c(), bl, Cm.get(), i, prm.Dmax, prm.svd_cutoff, dir == 0);
         if (last_bond) {
@@ -111,15 +115,22 @@ Mps* fit(Contractor& C, const MpoHost* H, cplx alpha, const Mps* psi, const std:
             form_theta(C, Cm.get(), 0, tf.c(), bl);
             dev_d2h(fin.data(), tf.c(), bl.size * sizeof(cplx), C.ctx->stream);
           }
-          double re = 0, im = 0;
-          for (int64_t x = 0; x < bl.size; ++x) {
-            re += fin[x].x * h_local[x].x + fin[x].y * h_local[x].y;
-            im += fin[x].x * h_local[x].y - fin[x].y * h_local[x].x;
+          auto dot = [&](const std::vector<cplx>& v) {
+            double re = 0, im = 0;
+            for (int64_t x = 0; x < (int64_t)v.size(); ++x) {
+              re += fin[x].x * v[x].x + fin[x].y * v[x].y;
+              im += fin[x].x * v[x].y - fin[x].y * v[x].x;
+            }
+            return cplx{re, im};
+          };
+          out.term_overlaps.clear();
+          for (size_t k = 0; k < T.size(); ++k) {
+            const cplx d = dot(local[k]);
+            if (H && k == 0)
+              out.h_out_psi = d;
+            else
+              out.term_overlaps.push_back(d);
           }
-          // the H term carried alpha
-          const double a2 = alpha.x * alpha.x + alpha.y * alpha.y;
-          out.h_out_psi = a2 > 0 ? cplx{(re * alpha.x + im * alpha.y) / a2, (im * alpha.x - re * alpha.y) / a2}
-                                 : cplx{0, 0};
         }
         out.disc_max = std::max(out.disc_max, tr.discarded);
         out.disc_sum += tr.discarded;

@@ -524,8 +524,8 @@ static MpoHost build_identity_mpo(int L) {
 // One operator per length, so that its version (and the premix structures cached under it)
 // stays the same from call to call.
 MpoHost identity_mpo(int L) {
-  static std::mutex mu;
-  static std::map<int, MpoHost> made;
+  static std::mutex& mu = *new std::mutex;
+  static std::map<int, MpoHost>& made = *new std::map<int, MpoHost>;
   std::lock_guard<std::mutex> lk(mu);
   auto it = made.find(L);
   if (it == made.end()) it = made.emplace(L, build_identity_mpo(L)).first;
