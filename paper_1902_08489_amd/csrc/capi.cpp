@@ -586,10 +586,10 @@ extern "C" tdmps_status tdmps_heff_apply(tdmps_heff h, const void* in, void* out
       c->counters[1] = h->plan->p1.flops;
       c->counters[2] = h->plan->p2.flops;
       c->counters[3] = (double)h->plan->T.bytes;
-      c->counters[4] = (double)h->plan->p1.tasks.size();
-      c->counters[5] = (double)h->plan->p2.tasks.size();
-      c->counters[6] = (double)h->plan->p1.segs.size();
-      c->counters[7] = (double)h->plan->p2.segs.size();
+      c->counters[4] = (double)h->plan->p1.task_count();
+      c->counters[5] = (double)h->plan->p2.task_count();
+      c->counters[6] = (double)h->plan->p1.seg_count();
+      c->counters[7] = (double)h->plan->p2.seg_count();
     }
     if (c->batched == 2) {
       if (!h->graph) {

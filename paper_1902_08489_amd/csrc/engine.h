@@ -236,12 +236,17 @@ struct GemmPlan {
   int ntask[NCFG] = {};
   int64_t ntiles[NCFG] = {};
   bool final_ = false;
+  // task and segment counts as built (finalize hands the host lists back to a per-thread
+  // pool, so that their capacity is reused by the next plan instead of faulted in again)
+  size_t ntasks_built = 0, nsegs_built = 0;
+  size_t task_count() const { return final_ ? ntasks_built : tasks.size(); }
+  size_t seg_count() const { return final_ ? nsegs_built : segs.size(); }
   void finalize(Ctx* ctx, int precision);
   // batched: one grouped launch per tile shape (default); else one launch per task (the
   // per-block baseline the grouped launch is compared with)
   void launch(Ctx* ctx, int precision, bool batched = true);
   void run(Ctx* ctx, int precision, bool batched = true);  // finalize + launch + synchronise
-  bool empty() const { return tasks.empty(); }
+  bool empty() const { return task_count() == 0; }
 };
 
 struct CopyPlan {

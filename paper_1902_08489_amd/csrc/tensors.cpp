@@ -105,7 +105,35 @@ void Blocks::layout(const Bond& b, const Bond& k, const std::vector<std::pair<Ch
 }
 
 // ---------------------------------------------------------------- plans
+// Per-thread pools of host vectors for plan building: the large lists of a plan (hundreds of
+// thousands of segments at the L = 24, D = 1024 centre) are reused with their capacity, which
+// saves the growth copies and the page faults of fresh allocations on every plan.
+namespace {
+template <class T>
+struct VecPool {
+  std::vector<std::vector<T>> free;
+  std::vector<T> take() {
+    if (free.empty()) return {};
+    std::vector<T> v = std::move(free.back());
+    free.pop_back();
+    v.clear();
+    return v;
+  }
+  void give(std::vector<T>& v) {
+    constexpr size_t MAX_BYTES = (size_t)256 << 20;
+    if (v.capacity() == 0 || v.capacity() * sizeof(T) > MAX_BYTES || free.size() >= 8) return;
+    v.clear();
+    free.push_back(std::move(v));
+    v = std::vector<T>();
+  }
+};
+thread_local VecPool<GemmTask> t_task_pool;
+thread_local VecPool<GemmSeg> t_seg_pool;
+thread_local VecPool<char> t_img_pool;
+}  // namespace
+
 int GemmPlan::begin_task(cplx* C, int64_t bsC, int ldc, int m, int n, int nbatch, bool accum) {
+  if (tasks.capacity() == 0) tasks = t_task_pool.take();
   GemmTask t;
   t.C = C;
   t.bsC = bsC;
@@ -124,6 +152,7 @@ int GemmPlan::begin_task(cplx* C, int64_t bsC, int ldc, int m, int n, int nbatch
 
 void GemmPlan::add_seg(const cplx* A, int64_t bsA, int64_t rsA, int lda, int opA, const cplx* B, int64_t bsB,
                        int64_t rsB, int ldb, int opB, int k, int nred, cplx alpha) {
+  if (segs.capacity() == 0) segs = t_seg_pool.take();
   GemmSeg s;
   s.A = A;
   s.B = B;
@@ -147,22 +176,37 @@ void GemmPlan::add_seg(const cplx* A, int64_t bsA, int64_t rsA, int lda, int opA
 void GemmPlan::finalize(Ctx* ctx, int precision) {
   if (final_) return;
   final_ = true;
-  // drop tasks without work that do not need to overwrite their output
-  std::vector<GemmTask> keep;
-  keep.reserve(tasks.size());
-  for (auto& t : tasks)
-    if (t.m > 0 && t.n > 0 && t.nbatch > 0 && (t.nseg > 0 || !(t.flags & GEMM_ACCUM))) keep.push_back(t);
-  if (keep.empty()) return;
+  ntasks_built = tasks.size();
+  nsegs_built = segs.size();
+  struct Release {
+    GemmPlan& p;
+    ~Release() {
+      t_task_pool.give(p.tasks);
+      t_seg_pool.give(p.segs);
+    }
+  } release_{*this};
   // Split-K: a task whose reduction is long (many channels) is cut into parts of about
   // KSPLIT complex k; parts write private partial outputs that a reduction kernel adds in
   // a fixed order (deterministic, no atomics).
   const int64_t KSPLIT = 1024;
-  std::vector<GemmTask> out;
-  std::vector<GemmSeg> nsegs;
+  std::vector<GemmTask> out = t_task_pool.take();
+  std::vector<GemmSeg> nsegs = t_seg_pool.take();
+  struct Scratch {
+    std::vector<GemmTask>& out;
+    std::vector<GemmSeg>& nsegs;
+    ~Scratch() {
+      t_task_pool.give(out);
+      t_seg_pool.give(nsegs);
+    }
+  } scratch_{out, nsegs};
+  out.reserve(tasks.size());
+  nsegs.reserve(segs.size());
   std::vector<ReduceTask> red;
   std::vector<std::pair<size_t, int64_t>> part_of;  // (task index in out, offset in workspace)
   int64_t ws = 0;
-  for (auto& t : keep) {
+  for (auto& t : tasks) {
+    // drop tasks without work that do not need to overwrite their output
+    if (!(t.m > 0 && t.n > 0 && t.nbatch > 0 && (t.nseg > 0 || !(t.flags & GEMM_ACCUM)))) continue;
     int64_t work = 0;
     for (int s = t.seg0; s < t.seg0 + t.nseg; ++s) work += (int64_t)segs[s].nred * segs[s].k;
     int nparts = (t.nbatch == 1 && work > 2 * KSPLIT) ? (int)std::min<int64_t>(64, (work + KSPLIT - 1) / KSPLIT) : 1;
@@ -222,6 +266,7 @@ void GemmPlan::finalize(Ctx* ctx, int precision) {
     red.push_back(rt);
     red_base.push_back(base);
   }
+  if (out.empty()) return;
   if (ws > 0) {
     wspace = DevBuf(ws * sizeof(cplx));
     for (auto& po : part_of) out[po.first].C = wspace.c() + po.second;
@@ -297,7 +342,12 @@ void GemmPlan::finalize(Ctx* ctx, int precision) {
     o_tile[cfg] = bytes;
     bytes = align(bytes + tmap[cfg].size() * sizeof(int32_t));
   }
-  std::vector<char> img(bytes);
+  std::vector<char> img = t_img_pool.take();
+  struct ImgBack {
+    std::vector<char>& v;
+    ~ImgBack() { t_img_pool.give(v); }
+  } img_back_{img};
+  img.resize(bytes);
   if (!nsegs.empty()) std::memcpy(img.data() + o_segs, nsegs.data(), nsegs.size() * sizeof(GemmSeg));
   if (!red.empty()) std::memcpy(img.data() + o_red, red.data(), red.size() * sizeof(ReduceTask));
   for (int cfg = 0; cfg < NCFG; ++cfg) {
