@@ -251,7 +251,7 @@ def test_mps_sequential_svd_exact_and_truncation_weight():
     assert max(mt.bond_dims()) <= 12
 
 
-def test_dfci_matches_survey_counts():
+def test_dfci_matches_combinatorial_counts():
     assert mps.dfci_bonds(8, (3, 4))[4] == 160
     assert mps.dfci_bonds(10, (4, 5))[5] == 704
 
