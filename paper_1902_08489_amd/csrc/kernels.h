@@ -126,7 +126,7 @@ void launch_svd_init(const SvdMat* mats, int nmats, void* stream);  // V = ident
 // prev_counter is given and holds 0 (the previous sweep rotated nothing: converged), the
 // round does nothing, so sweeps can be queued ahead of the convergence test.
 void launch_svd_round(const SvdMat* mats, int nmats, int64_t total_pairs, int round, double tol, int32_t* rot_counter,
-                      const int32_t* prev_counter, void* stream);
+                      const int32_t* prev_counter, int waves, void* stream);
 void launch_svd_norms(const SvdMat* mats, int nmats, int max_k, double* sigma_out, void* stream);
 void launch_scale(cplx* x, int64_t n, cplx alpha, void* stream);
 // QR preconditioning of the Jacobi SVD: factor panel j0 (one workgroup per matrix); apply

@@ -147,7 +147,6 @@ __device__ __forceinline__ bool make_rot(double a, double b, double gr, double g
 // D[l/16 + 4e][l%16] in register e.  For the Gram matrix both operands are the element
 // P[4s + l/16][l%16] of the 4-row step s.  Every wave issues the loads of a whole batch of
 // steps (tiles) before its first MFMA, so a block pair's panel is in flight at once.
-constexpr int SVD_WAVES = 8;
 constexpr int SVD_GB = 16;  // Gram: 4-row steps per wave and batch
 constexpr int SVD_UB = 4;   // update: 16-row tiles per wave and batch
 
@@ -157,13 +156,18 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__global__ __launch_bounds__(64 * SVD_WAVES) void svd_block_round_kernel(const SvdMat* __restrict__ mats, int nmats,
+// WAVES waves per workgroup (4 or 8): the Gram matrix and the column update are split over
+// the waves, the 16 x 16 rotation sweep runs on wave 0.  Small matrices run faster with 4
+// (fewer idle waves per barrier), large ones gain nothing from either.
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void svd_block_round_kernel(const SvdMat* __restrict__ mats, int nmats,
                                                                          int round, double tol,
                                                                          int32_t* __restrict__ counter,
                                                                          const int32_t* __restrict__ prev) {
   static_assert(SVD_PW == 16, "one 16 x 16 MFMA tile per block pair");
+  static_assert(WAVES >= 4, "the Gram reduction uses one thread per element of the 16 x 16 matrix");
   typedef double v4d __attribute__((ext_vector_type(4)));
-  __shared__ double2 Mp[SVD_WAVES][SVD_PW][SVD_PW + 1];  // per-wave partial Gram matrices
+  __shared__ double2 Mp[WAVES][SVD_PW][SVD_PW + 1];  // per-wave partial Gram matrices
   __shared__ double2 Ms[SVD_PW][SVD_PW + 1];
   __shared__ double2 Qs[SVD_PW][SVD_PW + 1];
   __shared__ int col[SVD_PW];
@@ -185,17 +189,17 @@ __global__ __launch_bounds__(64 * SVD_WAVES) void svd_block_round_kernel(const S
   if (t == 0) rotated = 0;
   __syncthreads();
 
-  // Gram matrix: wave w takes the 4-row steps w, w + SVD_WAVES, ...
+  // Gram matrix: wave w takes the 4-row steps w, w + WAVES, ...
   {
     const double2* G = (const double2*)m.G;
     const int c = col[l16];
     const int nsteps = (m.ell + 3) >> 2;
     v4d r1 = {0, 0, 0, 0}, r2 = r1, i1 = r1, i2 = r1;
-    for (int s0 = wave; s0 < nsteps; s0 += SVD_WAVES * SVD_GB) {
+    for (int s0 = wave; s0 < nsteps; s0 += WAVES * SVD_GB) {
       double2 v[SVD_GB];
 #pragma unroll
       for (int u = 0; u < SVD_GB; ++u) {
-        const int row = 4 * (s0 + SVD_WAVES * u) + lq;
+        const int row = 4 * (s0 + WAVES * u) + lq;
         v[u] = (c >= 0 && row < m.ell) ? G[(int64_t)c * m.ell + row] : make_double2(0.0, 0.0);
       }
 #pragma unroll
@@ -214,7 +218,7 @@ __global__ __launch_bounds__(64 * SVD_WAVES) void svd_block_round_kernel(const S
     const int a = t >> 4, b = t & 15;
     double sr = 0, si = 0;
 #pragma unroll
-    for (int w = 0; w < SVD_WAVES; ++w) {
+    for (int w = 0; w < WAVES; ++w) {
       sr += Mp[w][a][b].x;
       si += Mp[w][a][b].y;
     }
@@ -279,7 +283,7 @@ __global__ __launch_bounds__(64 * SVD_WAVES) void svd_block_round_kernel(const S
   if (!rotated) return;  // uniform: read after the barrier
   if (t == 0) atomicAdd(counter, 1);
 
-  // P <- P Q and V <- V Q in 16-row tiles, wave w taking tiles w, w + SVD_WAVES, ...; k-step
+  // P <- P Q and V <- V Q in 16-row tiles, wave w taking tiles w, w + WAVES, ...; k-step
   // s of a tile reads column 4s + l/16 at row l%16 (A operand) and keeps Q[4s + l/16][l%16]
   double qr[4], qi[4];
   int cin[4];
@@ -295,11 +299,11 @@ __global__ __launch_bounds__(64 * SVD_WAVES) void svd_block_round_kernel(const S
     double2* X = (double2*)(pass == 0 ? m.G : m.V);
     const int len = pass == 0 ? m.ell : m.k;
     const int ntiles = (len + 15) >> 4;
-    for (int t0 = wave; t0 < ntiles; t0 += SVD_WAVES * SVD_UB) {
+    for (int t0 = wave; t0 < ntiles; t0 += WAVES * SVD_UB) {
       double2 v[SVD_UB][4];
 #pragma unroll
       for (int u = 0; u < SVD_UB; ++u) {
-        const int row = 16 * (t0 + SVD_WAVES * u) + l16;
+        const int row = 16 * (t0 + WAVES * u) + l16;
 #pragma unroll
         for (int s = 0; s < 4; ++s)
           v[u][s] = (cin[s] >= 0 && row < len) ? X[(int64_t)cin[s] * len + row] : make_double2(0.0, 0.0);
@@ -314,7 +318,7 @@ __global__ __launch_bounds__(64 * SVD_WAVES) void svd_block_round_kernel(const S
           br = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u][s].y, -qi[s], br, 0, 0, 0);
           bi = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u][s].y, qr[s], bi, 0, 0, 0);
         }
-        const int tile = t0 + SVD_WAVES * u;
+        const int tile = t0 + WAVES * u;
         if (cout >= 0) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
@@ -357,10 +361,15 @@ void launch_svd_init(const SvdMat* mats, int nmats, void* stream) {
 }
 
 void launch_svd_round(const SvdMat* mats, int nmats, int64_t total_pairs, int round, double tol, int32_t* counter,
-                      const int32_t* prev, void* stream) {
+                      const int32_t* prev, int waves, void* stream) {
   if (nmats <= 0 || total_pairs <= 0) return;
-  hipLaunchKernelGGL(svd_block_round_kernel, dim3((unsigned)total_pairs), dim3(64 * SVD_WAVES), 0, (hipStream_t)stream, mats,
-                     nmats, round, tol, counter, prev);
+  TDMPS_REQUIRE(waves == 4 || waves == 8, TDMPS_ERR_ARG, "svd round: waves must be 4 or 8");
+  if (waves == 4)
+    hipLaunchKernelGGL(svd_block_round_kernel<4>, dim3((unsigned)total_pairs), dim3(64 * 4), 0, (hipStream_t)stream,
+                       mats, nmats, round, tol, counter, prev);
+  else
+    hipLaunchKernelGGL(svd_block_round_kernel<8>, dim3((unsigned)total_pairs), dim3(64 * 8), 0, (hipStream_t)stream,
+                       mats, nmats, round, tol, counter, prev);
   check(hipGetLastError(), "svd round launch");
 }
 

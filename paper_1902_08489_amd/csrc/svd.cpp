@@ -154,6 +154,10 @@ struct SvdBatch {
     // rotated nothing skips on the device, so the host reads the counters once per batch.
     const double tol = 1e-15;
     const int max_sweeps = 60;
+    // four waves per block pair while every column is short (256 rows or fewer), eight beyond
+    int max_len = 0;
+    for (const SvdMat& x : xm) max_len = std::max(max_len, std::max(x.ell, x.k));
+    const int waves = max_len <= 256 ? 4 : 8;
     DevBuf counter(max_sweeps * sizeof(int32_t));
     int32_t* dc = (int32_t*)counter.p;
     dev_zero(counter.p, counter.bytes, ctx->stream);
@@ -164,7 +168,7 @@ struct SvdBatch {
       const int batch = std::min(max_sweeps - queued, queued == 0 ? 6 : 3);
       for (int sw = queued; sw < queued + batch; ++sw)
         for (int r = -1; r < maxrounds; ++r)
-          launch_svd_round(dm, nm, pairs, r, tol, dc + sw, sw > 0 ? dc + sw - 1 : nullptr, ctx->stream);
+          launch_svd_round(dm, nm, pairs, r, tol, dc + sw, sw > 0 ? dc + sw - 1 : nullptr, waves, ctx->stream);
       dev_d2h(rot.data() + queued, dc + queued, batch * sizeof(int32_t), ctx->stream);
       for (int sw = queued; sw < queued + batch && !converged; ++sw) {
         sweeps_done = sw + 1;
