@@ -488,3 +488,22 @@ def test_rdm_error_over_time(ctx, sys8):
         print(f"eps(t) {'orthogonal' if ortho else 'non-orthogonal'} basis: D=256 {eps[256]}, D=8 {eps[8]}")
         assert eps[256].max() < (1e-9 if ortho else 1e-7), (ortho, eps[256])
         assert np.all(np.isfinite(eps[8])) and 1e-6 < eps[8][-1] < 0.5, (ortho, eps[8])
+
+
+def test_compress_round_trip_long_columns(ctx):
+    """SVD truncation on sector matrices with columns longer than 256 rows (the eight-wave
+    Jacobi rounds): a random state at L = 12, N = 11, D = 1024 (sectors up to ~140, split
+    matrices up to ~560 rows) compressed with Dmax above its bond dimension reproduces
+    itself; capped at Dmax = 64 the result stays normalised to the kept weight."""
+    L, Nu, Nd, D = 12, 5, 6, 1024
+    bonds, data = synth.random_state(L, Nu, Nd, D, seed=31)
+    psi = T.MPS.from_blocks(ctx, bonds, data)
+    n2 = T.overlap(psi, psi).real
+    out, info = T.compress([(1.0, psi)], T.fit_params(Dmax=4096, n_sweeps=1))
+    assert abs(T.overlap(psi, out) / n2 - 1) < 1e-10
+    assert abs(T.overlap(out, out).real / n2 - 1) < 1e-10
+    assert max(out.bond_dims()) <= max(psi.bond_dims())
+    small, sinfo = T.compress([(1.0, psi)], T.fit_params(Dmax=64, n_sweeps=2))
+    assert max(small.bond_dims()) <= 64
+    f = abs(T.overlap(psi, small)) ** 2 / (n2 * T.overlap(small, small).real)
+    assert np.isfinite(f) and 0 < f <= 1 + 1e-12
