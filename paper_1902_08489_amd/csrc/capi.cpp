@@ -583,12 +583,12 @@ extern "C" tdmps_status tdmps_heff_apply(tdmps_heff h, const void* in, void* out
       h->plan_gen = c->tune_gen;
       h->alg_flops = h->plan->alg_flops;
       c->counters[0] = h->alg_flops;
-      c->counters[1] = h->plan->p1.flops;
+      c->counters[1] = h->plan->p1.flops + h->plan->p1b.flops;
       c->counters[2] = h->plan->p2.flops;
       c->counters[3] = (double)h->plan->T.bytes;
-      c->counters[4] = (double)h->plan->p1.task_count();
+      c->counters[4] = (double)(h->plan->p1.task_count() + h->plan->p1b.task_count());
       c->counters[5] = (double)h->plan->p2.task_count();
-      c->counters[6] = (double)h->plan->p1.seg_count();
+      c->counters[6] = (double)(h->plan->p1.seg_count() + h->plan->p1b.seg_count());
       c->counters[7] = (double)h->plan->p2.seg_count();
     }
     if (c->batched == 2) {

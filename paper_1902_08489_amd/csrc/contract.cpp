@@ -13,6 +13,7 @@
 // GEMM over the channel index.  Consecutive middle channels with the same structure form
 // "runs" whose blocks are stacked, so each block product is one batched GEMM over a run.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -245,6 +246,17 @@ bool same_structure(const ChanOps& a, const ChanOps& b) {
     if (x.src != y.src || x.grp != y.grp || x.idx + 1 != y.idx || x.coef != y.coef) return false;
   }
   return true;
+}
+
+// How pattern k continues from channel a to the next channel b: 1 = stacked (consecutive
+// blocks of one stack, equal coefficient), 2 = shared (the same environment block for both,
+// each with its own coefficient: a single source such as a pair on the site weighted by an
+// integral), 0 = neither.
+int pattern_step(const OpRef& x, const OpRef& y, const Blocks* env) {
+  if (x.src != y.src || x.grp != y.grp) return 0;
+  if (x.idx + 1 == y.idx && x.coef == y.coef) return 1;
+  if (x.src == env && x.idx == y.idx) return 2;
+  return 0;
 }
 
 // Maximal ranges of middle channels with identical structure on the given sides.
@@ -527,6 +539,7 @@ Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, co
 void HeffPlan::launch(Ctx* ctx, int precision, bool batched) {
   if (!accumulate && out_size) dev_zero(out, out_size * sizeof(cplx), ctx->stream);
   p1.launch(ctx, precision, batched);
+  p1b.launch(ctx, precision, batched);
   p2.launch(ctx, precision, batched);
 }
 
@@ -538,7 +551,7 @@ void heff_apply(Contractor& C, const SideOps& lops, const SideOps& rops, const c
   C.t_plan += wall_seconds() - t0;
   plan->launch(C.ctx, C.precision, C.batched);
   if (C.ctx->phase_sync) dev_sync(C.ctx->stream);
-  C.heff_flops += plan->p1.flops + plan->p2.flops;
+  C.heff_flops += plan->p1.flops + plan->p1b.flops + plan->p2.flops;
   if (alg_flops) *alg_flops = plan->alg_flops;
   C.t_heff += wall_seconds() - t0;
   C.n_heff += 1;
@@ -554,15 +567,32 @@ std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const Si
   plan->out_size = bl.size;
   plan->accumulate = accumulate;
   const int nmid = (int)lops.ch.size();
-  // runs over the middle cut with identical structure on both sides
+  // Runs over the middle cut: identical structure on the right; on the left every pattern
+  // either stacked over the run or shared by all of its channels (shared[r][k]).  Shared
+  // patterns are computed per channel in a stage of their own (p1b below), the rest as one
+  // product over the whole run.
   std::vector<Run> runs;
+  std::vector<std::vector<char>> shared;
   {
+    const Blocks* lenv = &lops.env->b;
     int v = 0;
     while (v < nmid) {
+      const ChanOps& c0 = lops.ch[v];
+      std::vector<char> kind(c0.pat.size(), 0);
       int e = v + 1;
-      while (e < nmid && same_structure(lops.ch[e - 1], lops.ch[e]) && same_structure(rops.ch[e - 1], rops.ch[e]))
+      while (e < nmid && lops.ch[e].pat == c0.pat && same_structure(rops.ch[e - 1], rops.ch[e])) {
+        bool ok = true;
+        for (size_t k = 0; k < c0.pat.size() && ok; ++k) {
+          const int step = pattern_step(lops.ch[e - 1].ref[k], lops.ch[e].ref[k], lenv);
+          if (step == 0 || (kind[k] != 0 && kind[k] != step)) ok = false;
+        }
+        if (!ok) break;
+        for (size_t k = 0; k < c0.pat.size(); ++k) kind[k] = (char)pattern_step(lops.ch[e - 1].ref[k], lops.ch[e].ref[k], lenv);
         ++e;
+      }
+      for (auto& x : kind) x = x == 2;
       runs.push_back({v, e - v});
+      shared.push_back(std::move(kind));
       v = e;
     }
   }
@@ -627,56 +657,110 @@ std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const Si
   // T stage
   int64_t tsize = 0;
   GemmPlan& p1 = plan->p1;
+  GemmPlan& p1b = plan->p1b;
   std::vector<size_t> row_task(rows.size(), (size_t)-1);
+  struct SharedTask {
+    size_t task, row;
+    int j;
+  };
+  std::vector<SharedTask> shared_tasks;
   for (size_t ri = 0; ri < rows.size(); ++ri) {
     Row& R = rows[ri];
     const Run& run = runs[R.r];
     const ChanOps& lo = lops.ch[run.v0];
     const int Ds = bra_l.dim[R.s];
-    bool started = false;
+    // contributing patterns of this row block and its columns: every s2' between the lowest
+    // and highest needed one whose ket sector exists, taken from the first pattern
+    std::vector<int> pats;
     for (size_t k = 0; k < lo.pat.size(); ++k) {
       if ((lo.pat[k] >> 2) != R.s1) continue;
-      const int s1p = lo.pat[k] & 3;
+      const OpRef& ref = lo.ref[k];
+      if (ref.src->grp[ref.grp].ket_of[R.s] < 0) continue;
+      pats.push_back((int)k);
+    }
+    if (pats.empty()) continue;
+    {
+      const OpRef& ref = lo.ref[pats[0]];
+      const int sk = ref.src->grp[ref.grp].ket_of[R.s];
+      const int s1p = lo.pat[pats[0]] & 3;
+      for (int q = 0; q < 4; ++q)
+        if (R.mask >> q & 1) {
+          R.lo = std::min(R.lo, q);
+          R.hi = std::max(R.hi, q);
+        }
+      for (int q = R.lo; q <= R.hi; ++q) {
+        const int tk = kl.rs[sk][s1p * 4 + q];
+        TDMPS_REQUIRE(R.tk[q] < 0 || R.tk[q] == tk, TDMPS_ERR_NUMERIC, "internal: theta column sector");
+        R.tk[q] = tk;
+        R.coff[q] = R.width;
+        if (tk >= 0) R.width += ket_r.dim[tk];
+      }
+    }
+    if (R.width == 0) continue;
+    R.off = tsize;
+    tsize += (int64_t)run.n * Ds * R.width;
+    // operands of pattern k: the ket-sector block of the left operator and the theta columns
+    auto operands = [&](int k, const cplx*& A, const cplx*& B, int& Dsk) {
       const OpRef& ref = lo.ref[k];
       const int sk = ref.src->grp[ref.grp].ket_of[R.s];
-      if (sk < 0) continue;
-      if (!started) {
-        // columns: every s2' between the lowest and highest needed one whose ket sector exists
-        for (int q = 0; q < 4; ++q)
-          if (R.mask >> q & 1) {
-            R.lo = std::min(R.lo, q);
-            R.hi = std::max(R.hi, q);
-          }
-        for (int q = R.lo; q <= R.hi; ++q) {
-          const int tk = kl.rs[sk][s1p * 4 + q];
-          TDMPS_REQUIRE(R.tk[q] < 0 || R.tk[q] == tk, TDMPS_ERR_NUMERIC, "internal: theta column sector");
-          R.tk[q] = tk;
-          R.coff[q] = R.width;
-          if (tk >= 0) R.width += ket_r.dim[tk];
-        }
-        if (R.width == 0) break;
-        R.off = tsize;
-        tsize += (int64_t)run.n * Ds * R.width;
-        row_task[ri] = p1.tasks.size();
-        p1.begin_task(nullptr, 0, R.width, run.n * Ds, R.width, 1, false);
-        started = true;
-      }
+      const int s1p = lo.pat[k] & 3;
       int first = -1;
       for (int q = R.lo; q <= R.hi; ++q) {
         const int tk = kl.rs[sk][s1p * 4 + q];
         TDMPS_REQUIRE(tk == R.tk[q], TDMPS_ERR_NUMERIC, "internal: theta column sector");
         if (tk >= 0 && first < 0) first = q;
       }
-      const int Dsk = ket_l.dim[sk];
-      const cplx* A = ref.src->stack(ref.grp, sk) + (int64_t)ref.idx * Ds * Dsk;
-      const cplx* B = theta_in + kl.panel_off[sk] + kl.col[sk][s1p * 4 + first];
-      p1.add_seg(A, 0, 0, Dsk, OP_N, B, 0, 0, kl.width[sk], OP_N, Dsk, 1, cplx{ref.coef, 0.0});
+      Dsk = ket_l.dim[sk];
+      A = ref.src->stack(ref.grp, sk) + (int64_t)ref.idx * Ds * Dsk;
+      B = theta_in + kl.panel_off[sk] + kl.col[sk][s1p * 4 + first];
+      return sk;
+    };
+    // stacked patterns: one product over all channels of the run
+    bool main_task = false;
+    for (int k : pats) {
+      if (run.n > 1 && shared[R.r][k]) continue;
+      const cplx *A, *B;
+      int Dsk;
+      const int sk = operands(k, A, B, Dsk);
+      if (!main_task) {
+        row_task[ri] = p1.tasks.size();
+        p1.begin_task(nullptr, 0, R.width, run.n * Ds, R.width, 1, false);
+        main_task = true;
+      }
+      p1.add_seg(A, 0, 0, Dsk, OP_N, B, 0, 0, kl.width[sk], OP_N, Dsk, 1, cplx{lo.ref[k].coef, 0.0});
+    }
+    // shared patterns: the same block for every channel, each with its own coefficient, into
+    // that channel's rows (after the stacked products, which write the row block first)
+    if (run.n > 1) {
+      bool any = false;
+      for (int k : pats) any |= shared[R.r][k] != 0;
+      if (any)
+        for (int j = 0; j < run.n; ++j) {
+          const ChanOps& cj = lops.ch[run.v0 + j];
+          bool opened = false;
+          for (int k : pats) {
+            if (!shared[R.r][k]) continue;
+            const cplx *A, *B;
+            int Dsk;
+            const int sk = operands(k, A, B, Dsk);
+            if (!opened) {
+              shared_tasks.push_back({p1b.tasks.size(), ri, j});
+              p1b.begin_task(nullptr, 0, R.width, Ds, R.width, 1, main_task);
+              opened = true;
+            }
+            p1b.add_seg(A, 0, 0, Dsk, OP_N, B, 0, 0, kl.width[sk], OP_N, Dsk, 1, cplx{cj.ref[k].coef, 0.0});
+          }
+        }
     }
   }
   plan->T = DevBuf(tsize * sizeof(cplx));
   cplx* Tb = plan->T.c();
   for (size_t ri = 0; ri < rows.size(); ++ri)
     if (row_task[ri] != (size_t)-1) p1.tasks[row_task[ri]].C = Tb + rows[ri].off;
+  for (const auto& st : shared_tasks) {
+    const Row& R = rows[st.row];
+    p1b.tasks[st.task].C = Tb + R.off + (int64_t)st.j * bra_l.dim[R.s] * R.width;
+  }
   // final stage
   GemmPlan& p2 = plan->p2;
   for (size_t ob = 0; ob < oblk.size(); ++ob) {
@@ -728,6 +812,7 @@ std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const Si
     plan->alg_flops = alg;
   }
   p1.finalize(C.ctx, C.precision);
+  p1b.finalize(C.ctx, C.precision);
   p2.finalize(C.ctx, C.precision);
   return plan;
 }

@@ -304,7 +304,7 @@ Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, co
 
 // theta_out (bra two-site layout) (+)= alpha * H_eff theta_in (ket two-site layout)
 struct HeffPlan {
-  GemmPlan p1, p2;
+  GemmPlan p1, p1b, p2;  // T stage (stacked over runs), T stage (shared blocks per channel), final stage
   DevBuf T;
   cplx* out = nullptr;
   int64_t out_size = 0;

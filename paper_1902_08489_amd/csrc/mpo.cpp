@@ -71,14 +71,20 @@ int key_parity(uint64_t k) {
 
 // Order of channels inside a class: by type, then so that channels which pass
 // through a site unchanged keep their relative order on both sides of it.
+// Pair channels are ordered by the kinds and spins of their two operators before their
+// orbitals: channels that differ only in orbitals combine the same local matrix units of a
+// site tensor, so keeping them adjacent makes long runs of identical structure (one stacked
+// product instead of one product per channel).
 std::array<int64_t, 4> key_order(uint64_t k) {
   int t = key_type(k);
   int64_t a = key_a(k), b = key_b(k);
   int64_t sa = a ? (a - 1) >> 2 : -1, sb = b ? (b - 1) >> 2 : -1;
+  auto kind = [](int64_t code) -> int64_t { return code ? ((code - 1) & 3) * 2 + (((code - 1) >> 2) & 1) : 0; };
+  const int64_t sig = kind(a) * 8 + kind(b);
   switch (t) {
     case K_L1: return {t, sa, a, 0};
-    case K_L2: return {t, std::max(sa, sb), std::min(sa, sb), a * 4096 + b};
-    case K_R2: return {t, std::min(sa, sb), std::max(sa, sb), a * 4096 + b};
+    case K_L2: return {t, sig, std::max(sa, sb) * 4096 + std::min(sa, sb), a * 4096 + b};
+    case K_R2: return {t, sig, std::min(sa, sb) * 4096 + std::max(sa, sb), a * 4096 + b};
     case K_R1: return {t, sa, a, 0};
     default: return {t, 0, 0, 0};
   }
