@@ -259,17 +259,32 @@ int pattern_step(const OpRef& x, const OpRef& y, const Blocks* env) {
   return 0;
 }
 
-// Maximal ranges of middle channels with identical structure on the given sides.
-std::vector<Run> make_runs(const MpoCut& mc, const SideOps* a, const SideOps* b) {
+// Maximal ranges of channels of one class of the middle cut whose operators, pattern by
+// pattern, are either stacked over the range or one shared environment block with
+// per-channel coefficients (pattern_step); shared[r][k] marks the latter for run r.
+std::vector<Run> make_runs(const MpoCut& mc, const SideOps& ops, std::vector<std::vector<char>>& shared) {
   std::vector<Run> runs;
-  int n = mc.size();
+  shared.clear();
+  const Blocks* env = &ops.env->b;
+  const int n = mc.size();
   int v = 0;
   while (v < n) {
+    const ChanOps& c0 = ops.ch[v];
+    std::vector<char> kind(c0.pat.size(), 0);
     int e = v + 1;
-    while (e < n && mc.cls_of[e] == mc.cls_of[v] && (!a || same_structure(a->ch[e - 1], a->ch[e])) &&
-           (!b || same_structure(b->ch[e - 1], b->ch[e])))
+    while (e < n && mc.cls_of[e] == mc.cls_of[v] && ops.ch[e].pat == c0.pat) {
+      bool ok = true;
+      for (size_t k = 0; k < c0.pat.size() && ok; ++k) {
+        const int step = pattern_step(ops.ch[e - 1].ref[k], ops.ch[e].ref[k], env);
+        if (step == 0 || (kind[k] != 0 && kind[k] != step)) ok = false;
+      }
+      if (!ok) break;
+      for (size_t k = 0; k < c0.pat.size(); ++k) kind[k] = (char)pattern_step(ops.ch[e - 1].ref[k], ops.ch[e].ref[k], env);
       ++e;
+    }
+    for (auto& x : kind) x = x == 2;
     runs.push_back({v, e - v});
+    shared.push_back(std::move(kind));
     v = e;
   }
   return runs;
@@ -320,13 +335,15 @@ static std::vector<std::pair<Charge, int>> cut_groups(const MpoCut& c) {
 // (run p1 before p2); T holds the intermediate and must outlive both runs.
 void env_left_plan(const SideOps& ops, const cplx* bra_site, const SiteLayout& bl, const Bond& bra_l,
                    const Bond& bra_r, const cplx* ket_site, const SiteLayout& kl, const Bond& ket_l,
-                   const Bond& ket_r, const MpoHost& W, Ctx* ctx, GemmPlan& p1, GemmPlan& p2, DevBuf& T, Env& out) {
+                   const Bond& ket_r, const MpoHost& W, Ctx* ctx, GemmPlan& p1, GemmPlan& p1b, GemmPlan& p2, DevBuf& T,
+                   Env& out) {
   const MpoCut& mc = W.cut[ops.cut];
   out.cut = ops.cut;
   out.b.layout(bra_r, ket_r, cut_groups(mc));
   out.b.data = DevBuf(out.b.size * sizeof(cplx));
   if (out.b.size) dev_zero(out.b.data.p, out.b.data.bytes, ctx->stream);
-  auto runs = make_runs(mc, &ops, nullptr);
+  std::vector<std::vector<char>> shared;
+  auto runs = make_runs(mc, ops, shared);
   // T_v[s, sig, t'] = sum_{sig'} Lop_v^{sig sig'}[s, s'] A_ket[s', sig', t']
   struct TKey {
     int r, s, sig, tk;
@@ -358,25 +375,40 @@ void env_left_plan(const SideOps& ops, const cplx* bra_site, const SiteLayout& b
     const Run& run = runs[K.r];
     const ChanOps& co = ops.ch[run.v0];
     int Ds = bra_l.dim[K.s], Dt = ket_r.dim[K.tk];
-    bool started = false;
-    for (size_t k = 0; k < co.pat.size(); ++k) {
-      int sig = co.pat[k] >> 2, sigp = co.pat[k] & 3;
-      if (sig != K.sig) continue;
-      const OpRef& ref = co.ref[k];
-      const StackGroup& sg = ref.src->grp[ref.grp];
-      int sp = sg.ket_of[K.s];
-      if (sp < 0) continue;
-      if (kl.rs[sp][sigp] != K.tk) continue;
-      int Dsp = ket_l.dim[sp];
-      if (!started) {
-        p1.begin_task(T.c() + toff[t], 0, Dt, run.n * Ds, Dt, 1, false);
-        started = true;
+    bool started = false, any_shared = false;
+    for (int pass = 0; pass < 2; ++pass)  // stacked patterns over the run, then shared ones per channel
+      for (int j = 0; j < (pass == 0 ? 1 : run.n); ++j) {
+        bool opened = false;
+        for (size_t k = 0; k < co.pat.size(); ++k) {
+          int sig = co.pat[k] >> 2, sigp = co.pat[k] & 3;
+          if (sig != K.sig) continue;
+          if ((run.n > 1 && shared[K.r][k]) != (pass == 1)) continue;
+          const OpRef& ref = co.ref[k];
+          const StackGroup& sg = ref.src->grp[ref.grp];
+          int sp = sg.ket_of[K.s];
+          if (sp < 0) continue;
+          if (kl.rs[sp][sigp] != K.tk) continue;
+          int Dsp = ket_l.dim[sp];
+          const cplx* A = ref.src->stack(ref.grp, sp) + (int64_t)ref.idx * Ds * Dsp;
+          const cplx* B = ket_site + kl.panel_off[sp] + kl.col[sp][sigp];
+          if (pass == 0) {
+            if (!started) {
+              p1.begin_task(T.c() + toff[t], 0, Dt, run.n * Ds, Dt, 1, false);
+              started = true;
+            }
+            p1.add_seg(A, 0, 0, Dsp, OP_N, B, 0, 0, kl.width[sp], OP_N, Dsp, 1, cplx{ref.coef, 0.0});
+          } else {
+            if (!opened) {
+              p1b.begin_task(T.c() + toff[t] + (int64_t)j * Ds * Dt, 0, Dt, Ds, Dt, 1, started);
+              opened = true;
+              any_shared = true;
+            }
+            p1b.add_seg(A, 0, 0, Dsp, OP_N, B, 0, 0, kl.width[sp], OP_N, Dsp, 1,
+                        cplx{ops.ch[run.v0 + j].ref[k].coef, 0.0});
+          }
+        }
       }
-      const cplx* A = ref.src->stack(ref.grp, sp) + (int64_t)ref.idx * Ds * Dsp;
-      const cplx* B = ket_site + kl.panel_off[sp] + kl.col[sp][sigp];
-      p1.add_seg(A, 0, 0, Dsp, OP_N, B, 0, 0, kl.width[sp], OP_N, Dsp, 1, cplx{ref.coef, 0.0});
-    }
-    tnonzero[t] = started;
+    tnonzero[t] = started || any_shared;
   }
   // L'_v[t, t'] = sum_{s, sig} conj(C[s, sig, t])^T T_v[s, sig, t']
   size_t cursor = 0;
@@ -415,16 +447,17 @@ Env env_left_update(Contractor& C, const SideOps& ops, const Mps*, const cplx* b
                     const Bond& bra_l, const Bond& bra_r, const cplx* ket_site, const SiteLayout& kl,
                     const Bond& ket_l, const Bond& ket_r, const MpoHost& W) {
   const double t0 = wall_seconds();
-  GemmPlan p1, p2;
+  GemmPlan p1, p1b, p2;
   DevBuf T;
   Env out;
-  env_left_plan(ops, bra_site, bl, bra_l, bra_r, ket_site, kl, ket_l, ket_r, W, C.ctx, p1, p2, T, out);
+  env_left_plan(ops, bra_site, bl, bra_l, bra_r, ket_site, kl, ket_l, ket_r, W, C.ctx, p1, p1b, p2, T, out);
   const double tb = wall_seconds();
   p1.run(C.ctx, C.precision, C.batched);
+  p1b.run(C.ctx, C.precision, C.batched);
   p2.run(C.ctx, C.precision, C.batched);
   if (C.ctx->phase_sync) dev_sync(C.ctx->stream);
-  C.t_plan += (tb - t0) + p1.host_s + p2.host_s;
-  C.env_flops += p1.flops + p2.flops;
+  C.t_plan += (tb - t0) + p1.host_s + p1b.host_s + p2.host_s;
+  C.env_flops += p1.flops + p1b.flops + p2.flops;
   C.t_env += wall_seconds() - t0;
   C.n_env += 1;
   return out;
@@ -440,7 +473,8 @@ Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, co
   out.b.layout(bra_l, ket_l, cut_groups(mc));
   out.b.data = DevBuf(out.b.size * sizeof(cplx));
   if (out.b.size) dev_zero(out.b.data.p, out.b.data.bytes, C.ctx->stream);
-  auto runs = make_runs(mc, &ops, nullptr);
+  std::vector<std::vector<char>> shared;
+  auto runs = make_runs(mc, ops, shared);
   // T_v[s', sig, t] = sum_{sig'} A_ket[s', sig', t'] Rop_v^{sig sig'}[t, t']^T
   struct TKey {
     int r, sk, sig, tb;
@@ -465,35 +499,51 @@ Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, co
     }
   }
   DevBuf T(tsize * sizeof(cplx));
-  GemmPlan p1;
+  GemmPlan p1, p1b;
   std::vector<char> tnonzero(tkeys.size(), 0);
   for (size_t t = 0; t < tkeys.size(); ++t) {
     const TKey& K = tkeys[t];
     const Run& run = runs[K.r];
     const ChanOps& co = ops.ch[run.v0];
     int Dsk = ket_l.dim[K.sk], Dt = bra_r.dim[K.tb];
-    bool started = false;
-    for (size_t k = 0; k < co.pat.size(); ++k) {
-      int sig = co.pat[k] >> 2, sigp = co.pat[k] & 3;
-      if (sig != K.sig) continue;
-      const OpRef& ref = co.ref[k];
-      const StackGroup& sg = ref.src->grp[ref.grp];
-      int tk = sg.ket_of[K.tb];
-      if (tk < 0) continue;
-      if (kl.rs[K.sk][sigp] != tk) continue;
-      int Dtk = ket_r.dim[tk];
-      if (!started) {
-        p1.begin_task(T.c() + toff[t], (int64_t)Dsk * Dt, Dt, Dsk, Dt, run.n, false);
-        started = true;
+    bool started = false, any_shared = false;
+    for (int pass = 0; pass < 2; ++pass)  // stacked patterns batched over the run, then shared ones per channel
+      for (int j = 0; j < (pass == 0 ? 1 : run.n); ++j) {
+        bool opened = false;
+        for (size_t k = 0; k < co.pat.size(); ++k) {
+          int sig = co.pat[k] >> 2, sigp = co.pat[k] & 3;
+          if (sig != K.sig) continue;
+          if ((run.n > 1 && shared[K.r][k]) != (pass == 1)) continue;
+          const OpRef& ref = co.ref[k];
+          const StackGroup& sg = ref.src->grp[ref.grp];
+          int tk = sg.ket_of[K.tb];
+          if (tk < 0) continue;
+          if (kl.rs[K.sk][sigp] != tk) continue;
+          int Dtk = ket_r.dim[tk];
+          const cplx* A = ket_site + kl.panel_off[K.sk] + kl.col[K.sk][sigp];
+          const cplx* B = ref.src->stack(ref.grp, tk) + (int64_t)ref.idx * Dt * Dtk;
+          if (pass == 0) {
+            if (!started) {
+              p1.begin_task(T.c() + toff[t], (int64_t)Dsk * Dt, Dt, Dsk, Dt, run.n, false);
+              started = true;
+            }
+            p1.add_seg(A, 0, 0, kl.width[K.sk], OP_N, B, (int64_t)Dt * Dtk, 0, Dtk, OP_T, Dtk, 1, cplx{ref.coef, 0.0});
+          } else {
+            if (!opened) {
+              p1b.begin_task(T.c() + toff[t] + (int64_t)j * Dsk * Dt, 0, Dt, Dsk, Dt, 1, started);
+              opened = true;
+              any_shared = true;
+            }
+            p1b.add_seg(A, 0, 0, kl.width[K.sk], OP_N, B, 0, 0, Dtk, OP_T, Dtk, 1,
+                        cplx{ops.ch[run.v0 + j].ref[k].coef, 0.0});
+          }
+        }
       }
-      const cplx* A = ket_site + kl.panel_off[K.sk] + kl.col[K.sk][sigp];
-      const cplx* B = ref.src->stack(ref.grp, tk) + (int64_t)ref.idx * Dt * Dtk;
-      p1.add_seg(A, 0, 0, kl.width[K.sk], OP_N, B, (int64_t)Dt * Dtk, 0, Dtk, OP_T, Dtk, 1, cplx{ref.coef, 0.0});
-    }
-    tnonzero[t] = started;
+    tnonzero[t] = started || any_shared;
   }
   const double tb1 = wall_seconds();
   p1.run(C.ctx, C.precision, C.batched);
+  p1b.run(C.ctx, C.precision, C.batched);
   const double te1 = wall_seconds();
   // R'_v[s, s'] = sum_{sig, t} conj(C[s, sig, t]) T_v[s', sig, t]^T
   GemmPlan p2;
@@ -529,8 +579,8 @@ Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, co
   const double tb2 = wall_seconds();
   p2.run(C.ctx, C.precision, C.batched);
   if (C.ctx->phase_sync) dev_sync(C.ctx->stream);
-  C.t_plan += (tb1 - t0) + (tb2 - te1) + p1.host_s + p2.host_s;
-  C.env_flops += p1.flops + p2.flops;
+  C.t_plan += (tb1 - t0) + (tb2 - te1) + p1.host_s + p1b.host_s + p2.host_s;
+  C.env_flops += p1.flops + p1b.flops + p2.flops;
   C.t_env += wall_seconds() - t0;
   C.n_env += 1;
   return out;
@@ -901,7 +951,7 @@ std::vector<cplx> sandwich_many(Contractor& C, const MpoHost& O, const std::vect
     size_t j0 = 0;
     while (j0 < nb) {
       const double tp = wall_seconds();
-      GemmPlan P0, P1, P2;
+      GemmPlan P0, P1, P1b, P2;
       std::vector<SideOps> ops;
       std::vector<DevBuf> T;
       ops.reserve(nb - j0);
@@ -913,7 +963,7 @@ std::vector<cplx> sandwich_many(Contractor& C, const MpoHost& O, const std::vect
         ops.push_back(build_ops(C, E[j1], O, i, true, &P0));
         T.emplace_back();
         env_left_plan(ops.back(), b->site[i].c(), b->lay[i], b->bond[i], b->bond[i + 1], ket->site[i].c(),
-                      ket->lay[i], ket->bond[i], ket->bond[i + 1], O, C.ctx, P1, P2, T.back(), N[j1]);
+                      ket->lay[i], ket->bond[i], ket->bond[i + 1], O, C.ctx, P1, P1b, P2, T.back(), N[j1]);
         bytes += (double)T.back().bytes + (ops.back().mix ? (double)ops.back().mix->data.bytes : 0.0);
         ++j1;
       }
@@ -924,10 +974,11 @@ std::vector<cplx> sandwich_many(Contractor& C, const MpoHost& O, const std::vect
       const double te = wall_seconds();
       C.t_mix += te - tr;
       P1.run(C.ctx, C.precision, C.batched);
+      P1b.run(C.ctx, C.precision, C.batched);
       P2.run(C.ctx, C.precision, C.batched);
       if (C.ctx->phase_sync) dev_sync(C.ctx->stream);
-      C.t_plan += (tr - tp) + P0.host_s + P1.host_s + P2.host_s;
-      C.env_flops += P1.flops + P2.flops;
+      C.t_plan += (tr - tp) + P0.host_s + P1.host_s + P1b.host_s + P2.host_s;
+      C.env_flops += P1.flops + P1b.flops + P2.flops;
       C.t_env += wall_seconds() - te;
       C.n_env += (double)(j1 - j0);
       j0 = j1;
