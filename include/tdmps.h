@@ -106,7 +106,8 @@ tdmps_status tdmps_ctx_destroy(tdmps_ctx ctx);
  * H_eff applications, environment updates and sandwiches, out[15] = seconds in the QR
  * preconditioning, out[16] = host seconds spent building GEMM plans (included in the H_eff
  * and environment times), out[17] / out[18] = device allocations the caching allocator has
- * made so far in the process and the seconds spent in them, out[19] = 0.  After tdmps_heff_apply planning, out[0..7]
+ * made so far in the process and the seconds spent in them, out[19] = premix structures built
+ * so far in the process (misses of the cache of per-site coefficient matrices).  After tdmps_heff_apply planning, out[0..7]
  * describe the plan instead:
  * algorithmic flops, executed flops of the two stages, bytes of the intermediate, task and
  * segment counts of the two stages. */

@@ -60,6 +60,7 @@ void publish(Ctx* ctx, const Contractor& C) {
   ctx->counters[15] = C.t_qr;
   ctx->counters[16] = C.t_plan;
   dev_alloc_stats(&ctx->counters[17], &ctx->counters[18]);
+  ctx->counters[19] = tdmps::premix_structures_built();
 }
 
 void check_prm(const tdmps_fit_params* p) {

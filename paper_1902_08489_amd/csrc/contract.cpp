@@ -155,8 +155,12 @@ std::mutex& g_skel_mu = *new std::mutex;
 std::map<SkelKey, SkelEntry>& g_skel = *new std::map<SkelKey, SkelEntry>;
 uint64_t g_skel_clock = 0;
 size_t g_skel_bytes = 0;
-constexpr size_t SKEL_MAX_ENTRIES = 1024;
-constexpr size_t SKEL_MAX_BYTES = (size_t)2 << 30;
+// Bounds of the cache: the dense coefficient matrices of one L = 24 operator take a few GB
+// over all sites and both sides; a bound below the working set of a sweep would rebuild them
+// at every site (LRU thrashing).
+constexpr size_t SKEL_MAX_ENTRIES = 4096;
+constexpr size_t SKEL_MAX_BYTES = (size_t)16 << 30;
+uint64_t g_skel_built = 0;  // structures built so far (cache misses)
 
 // The coefficient buffer is uploaded on, and only read on, the stream of the key, so the
 // caching allocator's stream order covers its reuse after eviction.
@@ -169,6 +173,7 @@ std::shared_ptr<const PremixSkel> premix_skeleton(Ctx* ctx, const MpoHost& W, in
     return it->second.sk;
   }
   auto sk = make_skeleton(ctx, W, site, left);
+  ++g_skel_built;
   const size_t bytes = sk->wmat ? sk->wmat->bytes : 0;
   while (!g_skel.empty() && (g_skel.size() >= SKEL_MAX_ENTRIES || g_skel_bytes + bytes > SKEL_MAX_BYTES)) {
     auto oldest = g_skel.begin();
@@ -181,6 +186,15 @@ std::shared_ptr<const PremixSkel> premix_skeleton(Ctx* ctx, const MpoHost& W, in
   g_skel_bytes += bytes;
   return sk;
 }
+
+}  // namespace
+
+double premix_structures_built() {
+  std::lock_guard<std::mutex> lk(g_skel_mu);
+  return (double)g_skel_built;
+}
+
+namespace {
 
 // With ext != nullptr the premix products are appended to *ext (run by the caller) instead
 // of being run here.

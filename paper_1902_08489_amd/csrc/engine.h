@@ -295,6 +295,8 @@ Env env_right_boundary(Ctx* ctx, const Bond& braL, const Bond& ketL, int L);
 SideOps premix_left(Contractor& C, const Env& L, const MpoHost& W, int site);
 SideOps premix_right(Contractor& C, const Env& R, const MpoHost& W, int site);
 
+// Premix structures built so far in the process (misses of the per-operator cache).
+double premix_structures_built();
 Env env_left_update(Contractor& C, const SideOps& ops, const Mps* bra, const cplx* bra_site, const SiteLayout& bl,
                     const Bond& bra_l, const Bond& bra_r, const cplx* ket_site, const SiteLayout& kl,
                     const Bond& ket_l, const Bond& ket_r, const MpoHost& W);
