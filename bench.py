@@ -248,7 +248,8 @@ def main():
         bk, dk = synth.random_state(L, Nu, Nd, D, sigma=1.0, seed=L + 5)
         psi = T.MPS.from_blocks(ctx, bk, dk)
         prm = T.fit_params(Dmax=D, n_sweeps=1, precision=PREC[args.precision])
-        built0 = ctx.counters()[19]
+        c0 = ctx.counters()
+        built0, alloc0, alloc_s0 = c0[19], c0[17], c0[18]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(args.krylov):
@@ -267,6 +268,8 @@ def main():
                   "executed_tflops_average": executed / (dt / args.krylov) / 1e12,
                   "phase_seconds_synchronised": synced,
                   "premix_structures_built": int(cnt[19] - built0),
+                  "device_allocations": int(cnt[17] - alloc0),
+                  "device_allocation_seconds": cnt[18] - alloc_s0,
                   "phase_seconds_last_step": {"heff": cnt[2], "env": cnt[3], "svd": cnt[4], "svd_qr": cnt[15],
                                               "premix": cnt[5], "sandwich_total": cnt[6],
                                               "host_planning_in_heff_env": cnt[16]},

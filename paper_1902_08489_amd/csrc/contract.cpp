@@ -604,6 +604,11 @@ void HeffPlan::launch(Ctx* ctx, int precision, bool batched) {
   if (!accumulate && out_size) dev_zero(out, out_size * sizeof(cplx), ctx->stream);
   p1.launch(ctx, precision, batched);
   p1b.launch(ctx, precision, batched);
+  if (!share_host.empty()) {
+    TDMPS_REQUIRE(p1b.dextra != nullptr, TDMPS_ERR_NUMERIC, "internal: share tasks not uploaded");
+    launch_share((const ShareTask*)p1b.dextra, (const double*)(p1b.dextra + share_coef_off), (int)share_host.size(),
+                 share_max_blk, ctx->stream);
+  }
   p2.launch(ctx, precision, batched);
 }
 
@@ -719,15 +724,16 @@ std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const Si
     }
   }
   // T stage
-  int64_t tsize = 0;
+  int64_t tsize = 0, xsize = 0;
   GemmPlan& p1 = plan->p1;
   GemmPlan& p1b = plan->p1b;
   std::vector<size_t> row_task(rows.size(), (size_t)-1);
-  struct SharedTask {
-    size_t task, row;
-    int j;
+  struct SharedRow {
+    size_t row, share;
+    int64_t xoff;
+    std::vector<size_t> xtask;
   };
-  std::vector<SharedTask> shared_tasks;
+  std::vector<SharedRow> shared_rows;
   for (size_t ri = 0; ri < rows.size(); ++ri) {
     Row& R = rows[ri];
     const Run& run = runs[R.r];
@@ -793,37 +799,69 @@ std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const Si
       }
       p1.add_seg(A, 0, 0, Dsk, OP_N, B, 0, 0, kl.width[sk], OP_N, Dsk, 1, cplx{lo.ref[k].coef, 0.0});
     }
-    // shared patterns: the same block for every channel, each with its own coefficient, into
-    // that channel's rows (after the stacked products, which write the row block first)
+    // Shared patterns: the same block for every channel of the run, each channel with its own
+    // coefficient.  Their products X_q = A_q B_q are formed once per row block (p1b), then
+    // added into every channel's rows, T_j += sum_q c_jq X_q, by one elementwise pass (after
+    // the stacked products of p1, which write the row block first).
     if (run.n > 1) {
-      bool any = false;
-      for (int k : pats) any |= shared[R.r][k] != 0;
-      if (any)
-        for (int j = 0; j < run.n; ++j) {
-          const ChanOps& cj = lops.ch[run.v0 + j];
-          bool opened = false;
-          for (int k : pats) {
-            if (!shared[R.r][k]) continue;
-            const cplx *A, *B;
-            int Dsk;
-            const int sk = operands(k, A, B, Dsk);
-            if (!opened) {
-              shared_tasks.push_back({p1b.tasks.size(), ri, j});
-              p1b.begin_task(nullptr, 0, R.width, Ds, R.width, 1, main_task);
-              opened = true;
-            }
-            p1b.add_seg(A, 0, 0, Dsk, OP_N, B, 0, 0, kl.width[sk], OP_N, Dsk, 1, cplx{cj.ref[k].coef, 0.0});
-          }
+      std::vector<int> sh;
+      for (int k : pats)
+        if (shared[R.r][k]) sh.push_back(k);
+      TDMPS_REQUIRE((int)sh.size() <= SHARE_MAXQ, TDMPS_ERR_NUMERIC, "internal: too many shared patterns");
+      if (!sh.empty()) {
+        const int nq = (int)sh.size();
+        const int64_t blk = (int64_t)Ds * R.width;
+        SharedRow sr;
+        sr.row = ri;
+        sr.xoff = xsize;
+        xsize += nq * blk;
+        for (int q = 0; q < nq; ++q) {
+          const cplx *A, *B;
+          int Dsk;
+          const int sk = operands(sh[q], A, B, Dsk);
+          sr.xtask.push_back(p1b.tasks.size());
+          p1b.begin_task(nullptr, 0, R.width, Ds, R.width, 1, false);
+          p1b.add_seg(A, 0, 0, Dsk, OP_N, B, 0, 0, kl.width[sk], OP_N, Dsk, 1, cplx{1.0, 0.0});
         }
+        const size_t coff = plan->coef_host.size();
+        for (int j = 0; j < run.n; ++j)
+          for (int q = 0; q < nq; ++q) plan->coef_host.push_back(lops.ch[run.v0 + j].ref[sh[q]].coef);
+        ShareTask st{};
+        st.coff = (int64_t)coff;
+        st.blk = blk;
+        st.nrun = run.n;
+        st.nq = nq;
+        st.accum = main_task ? 1 : 0;
+        sr.share = plan->share_host.size();
+        plan->share_host.push_back(st);
+        plan->share_max_blk = std::max(plan->share_max_blk, blk);
+        shared_rows.push_back(sr);
+      }
     }
   }
   plan->T = DevBuf(tsize * sizeof(cplx));
   cplx* Tb = plan->T.c();
   for (size_t ri = 0; ri < rows.size(); ++ri)
     if (row_task[ri] != (size_t)-1) p1.tasks[row_task[ri]].C = Tb + rows[ri].off;
-  for (const auto& st : shared_tasks) {
-    const Row& R = rows[st.row];
-    p1b.tasks[st.task].C = Tb + R.off + (int64_t)st.j * bra_l.dim[R.s] * R.width;
+  if (!shared_rows.empty()) {
+    // the shared products get a buffer of their own: keeping T at the size of its rows keeps
+    // the caching allocator's reuse of the large T buffers from bond to bond
+    plan->X = DevBuf(xsize * sizeof(cplx));
+    cplx* Xb = plan->X.c();
+    for (const auto& sr : shared_rows) {
+      const Row& R = rows[sr.row];
+      const int64_t blk = (int64_t)bra_l.dim[R.s] * R.width;
+      for (size_t q = 0; q < sr.xtask.size(); ++q) p1b.tasks[sr.xtask[q]].C = Xb + sr.xoff + (int64_t)q * blk;
+      ShareTask& st = plan->share_host[sr.share];
+      st.T = Tb + R.off;
+      st.X = Xb + sr.xoff;
+    }
+    // the share tasks and their coefficients travel with p1b's task tables
+    const size_t tb = plan->share_host.size() * sizeof(ShareTask);
+    plan->share_coef_off = (tb + 255) & ~(size_t)255;
+    p1b.extra.assign(plan->share_coef_off + plan->coef_host.size() * sizeof(double), 0);
+    std::memcpy(p1b.extra.data(), plan->share_host.data(), tb);
+    std::memcpy(p1b.extra.data() + plan->share_coef_off, plan->coef_host.data(), plan->coef_host.size() * sizeof(double));
   }
   // final stage
   GemmPlan& p2 = plan->p2;

@@ -226,6 +226,9 @@ struct GemmPlan {
   static constexpr int NCFG = GEMM_NCFG;
   // all task tables of the plan in one device buffer (one upload)
   DevBuf dtab, wspace;
+  // caller data uploaded with the task tables (one upload per plan); device copy at dextra
+  std::vector<char> extra;
+  const char* dextra = nullptr;
   const GemmSeg* dsegs = nullptr;
   const GemmTask* dtasks[NCFG] = {};
   const int32_t* dtile[NCFG] = {};
@@ -306,8 +309,14 @@ Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, co
 
 // theta_out (bra two-site layout) (+)= alpha * H_eff theta_in (ket two-site layout)
 struct HeffPlan {
-  GemmPlan p1, p1b, p2;  // T stage (stacked over runs), T stage (shared blocks per channel), final stage
-  DevBuf T;
+  // T stage: p1 stacked over runs, p1b products of blocks shared by a run (combined into the
+  // channels' rows by the share pass); p2 final stage
+  GemmPlan p1, p1b, p2;
+  DevBuf T, X;  // T intermediate; products of shared blocks
+  std::vector<double> coef_host;
+  std::vector<ShareTask> share_host;  // uploaded with p1b's tables: [tasks][coefficients]
+  int64_t share_max_blk = 0;
+  size_t share_coef_off = 0;  // byte offset of the coefficients in p1b.extra
   cplx* out = nullptr;
   int64_t out_size = 0;
   bool accumulate = false;

@@ -44,6 +44,19 @@ struct ReduceTask {
   int32_t m, n, ldc, nparts, accum;
 };
 
+// ---------------------------------------------------------------- shared-block combination
+// T[j * blk + e] (+)= sum_{q < nq} coef[j * nq + q] * X[q * blk + e] for j < nrun, e < blk: the
+// contributions of blocks shared by a run of channels, each channel with its own real
+// coefficients (nq <= SHARE_MAXQ).
+constexpr int SHARE_MAXQ = 8;
+struct ShareTask {
+  cplx* T;
+  const cplx* X;
+  int64_t coff;  // first coefficient of the task in the coefficient array of the launch
+  int64_t blk;
+  int32_t nrun, nq, accum, pad;
+};
+
 // ---------------------------------------------------------------- strided block copies
 // dst[r*dst_ld + c] (+)= op(src[(ridx?ridx[r]:r)*src_rs + (cidx?cidx[c]:c)*src_cs]) * rs[r] * cs[c]
 struct CopyTask {
@@ -119,6 +132,7 @@ constexpr int GEMM_NCFG = 10;  // tile shape configurations of launch_gemm
 int gemm_tile_m(int cfg);
 int gemm_tile_n(int cfg);
 void launch_copy(const CopyTask* tasks, int ntasks, void* stream);
+void launch_share(const ShareTask* tasks, const double* coef, int ntasks, int64_t max_blk, void* stream);
 void launch_svd_init(const SvdMat* mats, int nmats, void* stream);  // V = identity
 // One round (block pairs of the circle schedule, round >= 0; or the diagonal round of a sweep,
 // round < 0) for all matrices; total_pairs = sum nblk/2; rot_counter is incremented once per

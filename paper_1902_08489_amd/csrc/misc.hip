@@ -1,6 +1,8 @@
 // Strided block copies and the batched block one-sided Jacobi SVD (FP64).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <string>
 
 #include "common.h"
@@ -331,6 +333,31 @@ __global__ __launch_bounds__(64 * WAVES) void svd_block_round_kernel(const SvdMa
   }
 }
 
+// One workgroup row per task; the y dimension strides over the elements of the block.
+__global__ __launch_bounds__(256) void share_kernel(const ShareTask* __restrict__ tasks,
+                                                    const double* __restrict__ coef) {
+  const ShareTask t = tasks[blockIdx.x];
+  const double* cf = coef + t.coff;
+  const double2* X = (const double2*)t.X;
+  double2* T = (double2*)t.T;
+  for (int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x; e < t.blk; e += (int64_t)gridDim.y * 256) {
+    double2 x[SHARE_MAXQ];
+#pragma unroll
+    for (int q = 0; q < SHARE_MAXQ; ++q) x[q] = q < t.nq ? X[q * t.blk + e] : make_double2(0.0, 0.0);
+    for (int j = 0; j < t.nrun; ++j) {
+      double2 s = t.accum ? T[j * t.blk + e] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < SHARE_MAXQ; ++q)
+        if (q < t.nq) {
+          const double c = cf[j * t.nq + q];
+          s.x += c * x[q].x;
+          s.y += c * x[q].y;
+        }
+      T[j * t.blk + e] = s;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void svd_norms_kernel(const SvdMat* __restrict__ mats, int nmats, int maxk,
                                                         double* __restrict__ out) {
   const int lane = threadIdx.x & 63;
@@ -352,6 +379,14 @@ void launch_copy(const CopyTask* tasks, int ntasks, void* stream) {
   if (ntasks <= 0) return;
   hipLaunchKernelGGL(copy_kernel, dim3(ntasks, COPY_SPLIT), dim3(256), 0, (hipStream_t)stream, tasks);
   check(hipGetLastError(), "copy launch");
+}
+
+void launch_share(const ShareTask* tasks, const double* coef, int ntasks, int64_t max_blk, void* stream) {
+  if (ntasks <= 0 || max_blk <= 0) return;
+  const int64_t y = std::min<int64_t>(64, (max_blk + 1023) / 1024);
+  hipLaunchKernelGGL(share_kernel, dim3(ntasks, (unsigned)std::max<int64_t>(1, y)), dim3(256), 0, (hipStream_t)stream,
+                     tasks, coef);
+  check(hipGetLastError(), "share launch");
 }
 
 void launch_svd_init(const SvdMat* mats, int nmats, void* stream) {

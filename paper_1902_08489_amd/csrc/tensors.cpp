@@ -342,6 +342,8 @@ void GemmPlan::finalize(Ctx* ctx, int precision) {
     o_tile[cfg] = bytes;
     bytes = align(bytes + tmap[cfg].size() * sizeof(int32_t));
   }
+  const size_t o_extra = bytes;
+  bytes = align(bytes + extra.size());
   std::vector<char> img = t_img_pool.take();
   struct ImgBack {
     std::vector<char>& v;
@@ -354,9 +356,11 @@ void GemmPlan::finalize(Ctx* ctx, int precision) {
     if (!sel[cfg].empty()) std::memcpy(img.data() + o_task[cfg], sel[cfg].data(), sel[cfg].size() * sizeof(GemmTask));
     if (!tmap[cfg].empty()) std::memcpy(img.data() + o_tile[cfg], tmap[cfg].data(), tmap[cfg].size() * sizeof(int32_t));
   }
+  if (!extra.empty()) std::memcpy(img.data() + o_extra, extra.data(), extra.size());
   dtab = DevBuf(bytes);
   dev_h2d(dtab.p, img.data(), bytes, ctx->stream);
   char* b = (char*)dtab.p;
+  dextra = extra.empty() ? nullptr : b + o_extra;
   dsegs = (const GemmSeg*)(b + o_segs);
   dred = red.empty() ? nullptr : (const ReduceTask*)(b + o_red);
   for (int cfg = 0; cfg < NCFG; ++cfg) {
