@@ -37,9 +37,16 @@ std::map<Key, std::multimap<size_t, void*>> g_free;
 std::unordered_map<void*, Block> g_block;
 thread_local Key tl_key{0, nullptr};  // set by dev_bind
 
+// Sizes below 1 MiB round to 512 bytes, below 64 MiB to 2 MiB; larger ones to quarter-octave
+// buckets (at most 25% over the request), so that the large per-bond intermediates, whose
+// sizes drift from bond to bond, keep hitting the blocks released by earlier bonds.
 size_t round_size(size_t b) {
   if (b < (1u << 20)) return (b + 511) & ~size_t(511);
-  return (b + (2u << 20) - 1) & ~((size_t(2) << 20) - 1);
+  if (b < (size_t(64) << 20)) return (b + (2u << 20) - 1) & ~((size_t(2) << 20) - 1);
+  size_t oct = size_t(64) << 20;
+  while (oct * 2 <= b) oct *= 2;
+  const size_t step = oct / 4;
+  return (b + step - 1) / step * step;
 }
 
 void release_cache() {
