@@ -102,3 +102,22 @@ def test_error_paths(lib):
     assert e.value.code == -1
     with pytest.raises(T.TdmpsError):
         T.MPO.from_integrals(None, np.zeros((1, 1)), np.zeros((1,) * 4))
+
+
+def test_fiedler_order_host(lib):
+    """Orbital order of the H2O section through the C ABI (host code only): the oracle's
+    permutation on scrambled integrals, a scrambled chain restored, NaN rejected."""
+    from oracle import ordering
+    rng = np.random.default_rng(12)
+    for L in (5, 9, 16):
+        h, eri, _ = synth.integrals(L, seed=70 + L)
+        P = rng.permutation(L)
+        hs, es = ordering.permute(h, eri, P)
+        assert list(T.fiedler_order(hs, es)) == list(ordering.fiedler_order(hs, es))
+        chain = np.diag(np.linspace(-1, 1, L)) - 0.5 * (np.eye(L, k=1) + np.eye(L, k=-1))
+        back = P[T.fiedler_order(chain[np.ix_(P, P)])]
+        assert list(back) in (list(range(L)), list(range(L))[::-1])
+    bad = np.eye(4)
+    bad[0, 2] = bad[2, 0] = np.inf
+    with pytest.raises(T.TdmpsError):
+        T.fiedler_order(bad)
