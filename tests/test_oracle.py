@@ -376,6 +376,30 @@ def test_slater_condon_at_large_L_single_double():
         assert abs(sc.element(m2, m) - sc.element(m, m2)) < 1e-12
 
 
+def test_field_driven_rk4_is_fourth_order_in_time():
+    """Stage times of the driven RK4 map (t, t+dt/2, t+dt/2, t+dt): for commuting diagonal H0 and
+    M the exact propagator is the phase exp(-i(e T + A m F(T))) with F the integral of the pulse
+    shape (adaptive quadrature, independent of the RK4 code).  The global error must fall 16x
+    per halving of dt; evaluating any stage at a wrong time leaves a first-order error."""
+    from scipy.integrate import quad
+    rng = np.random.default_rng(7)
+    e = rng.uniform(-1, 1, 6)
+    m = rng.uniform(-1, 1, 6)
+    psi0 = rng.standard_normal(6) + 1j * rng.standard_normal(6)
+    psi0 /= np.linalg.norm(psi0)
+    f = propagate.pulse_shape(2.0, 0.6, 0.3)
+    A, T = 0.7, 1.2
+    F = quad(f, 0.0, T, epsabs=1e-15, epsrel=1e-14, limit=200)[0]
+    exact = np.exp(-1j * (e * T + A * F * m)) * psi0
+    errs = []
+    for n in (15, 30, 60):
+        psi = propagate.rk4_field_forward(np.diag(e), np.diag(m), psi0, f, A, T / n, n)[-1]
+        errs.append(np.linalg.norm(psi - exact))
+    assert errs[-1] < 1e-8
+    for a, b in zip(errs, errs[1:]):
+        assert 14.0 < a / b < 18.0
+
+
 def test_dipole_gradient_matches_finite_differences():
     """Adjoint gradient of the discrete RK4 map under a pulse (H(t) = H0 + A f(t) M) against
     central differences of the forward map: O(h^2) agreement pins every stage adjoint."""
