@@ -312,7 +312,8 @@ def main():
         "check": check,
         "plan": {"executed_flops_T_stage": plan_stats[1], "executed_flops_final_stage": plan_stats[2],
                  "T_bytes": plan_stats[3], "tasks": [int(plan_stats[4]), int(plan_stats[5])],
-                 "segments": [int(plan_stats[6]), int(plan_stats[7])]},
+                 "segments": [int(plan_stats[6]), int(plan_stats[7])],
+                 "shared_environment_runs": int(plan_stats[8]), "shared_products_bytes": plan_stats[9]},
     }
     print(json.dumps(line), flush=True)
 

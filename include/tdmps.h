@@ -107,10 +107,11 @@ tdmps_status tdmps_ctx_destroy(tdmps_ctx ctx);
  * preconditioning, out[16] = host seconds spent building GEMM plans (included in the H_eff
  * and environment times), out[17] / out[18] = device allocations the caching allocator has
  * made so far in the process and the seconds spent in them, out[19] = premix structures built
- * so far in the process (misses of the cache of per-site coefficient matrices).  After tdmps_heff_apply planning, out[0..7]
- * describe the plan instead:
- * algorithmic flops, executed flops of the two stages, bytes of the intermediate, task and
- * segment counts of the two stages. */
+ * so far in the process (misses of the cache of per-site coefficient matrices).  After
+ * tdmps_heff_apply planning, out[0..9] describe the plan instead: algorithmic flops, executed
+ * flops of the two stages, bytes of the intermediate, task and segment counts of the two
+ * stages, the number of shared-environment runs (channels of one environment block with
+ * their own coefficients, summed by the share pass) and the bytes of their products. */
 #define TDMPS_NCOUNTERS 20
 tdmps_status tdmps_ctx_counters(tdmps_ctx ctx, double* out);
 tdmps_status tdmps_ctx_reset_counters(tdmps_ctx ctx);

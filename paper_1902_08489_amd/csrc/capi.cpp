@@ -591,6 +591,8 @@ extern "C" tdmps_status tdmps_heff_apply(tdmps_heff h, const void* in, void* out
       c->counters[5] = (double)h->plan->p2.task_count();
       c->counters[6] = (double)(h->plan->p1.seg_count() + h->plan->p1b.seg_count());
       c->counters[7] = (double)h->plan->p2.seg_count();
+      c->counters[8] = (double)h->plan->share_host.size();
+      c->counters[9] = (double)h->plan->X.bytes;
     }
     if (c->batched == 2) {
       if (!h->graph) {
