@@ -56,6 +56,25 @@ def test_hermitian_and_conserves_number_and_spin():
     assert np.abs(H * nd[None, :] - nd[:, None] * H).max() < 1e-12
 
 
+def test_fermion_operators_satisfy_canonical_anticommutation():
+    """Jordan-Wigner signs of the annihilators and hopping matrices on the whole Fock space of
+    L = 3 (six spin orbitals): {a_i, a_j} = 0, {a_i, a_j^+} = delta_ij, and every hopping
+    matrix a_i^+ a_j (its own sign code, used by every Hamiltonian and rdm) equals the product
+    of the annihilator and its adjoint; the number operator counts the set bits."""
+    L = 3
+    space = fci.Space.full(L)
+    a = [fci.annihilator(space, space, j).toarray() for j in range(2 * L)]
+    eye = np.eye(space.dim)
+    for i in range(2 * L):
+        for j in range(2 * L):
+            assert np.array_equal(a[i] @ a[j] + a[j] @ a[i], np.zeros_like(eye))
+            want = eye if i == j else np.zeros_like(eye)
+            assert np.array_equal(a[i] @ a[j].T + a[j].T @ a[i], want)
+            assert np.array_equal(fci.hop_matrix(space, i, j).toarray(), a[i].T @ a[j])
+    nop = sum(a[j].T @ a[j] for j in range(2 * L))
+    assert np.array_equal(np.diag(nop), fci.popcount(space.masks).astype(float))
+
+
 def test_hubbard_dimer_closed_form():
     """Two sites, hopping -t, on-site (ii|ii) = U: singlet ground energy
     (U - sqrt(U^2 + 16 t^2))/2 (integral convention V_ijkl = (ik|jl))."""
