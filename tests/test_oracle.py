@@ -270,6 +270,30 @@ def test_mps_sequential_svd_exact_and_truncation_weight():
     assert max(mt.bond_dims()) <= 12
 
 
+def test_right_canonical_form_keeps_the_state():
+    """Right canonicalisation of a truncated MPS: the contracted state is unchanged, sites
+    1..L-1 are right-orthonormal (sum over n, b of B B^H = 1), and every nonzero element
+    respects the charge rule label_{i+1}[b] = label_i[a] + q(n)."""
+    L = 5
+    space = fci.Space.sector(L, 2, 2)
+    rng = np.random.default_rng(17)
+    v = rng.standard_normal(space.dim) + 1j * rng.standard_normal(space.dim)
+    m, _ = mps.from_full(space.embed(v), L, (2, 2), Dmax=6)
+    r = mps.right_canonicalize(m)
+    a, b = mps.to_full(m), mps.to_full(r)
+    assert np.linalg.norm(a - b) < 1e-12 * np.linalg.norm(a)
+    for i in range(1, L):
+        B = r.tensors[i].reshape(r.tensors[i].shape[0], -1)
+        assert np.allclose(B @ B.conj().T, np.eye(B.shape[0]), atol=1e-12)
+    for i in range(L):
+        T = r.tensors[i]
+        ql, qr = r.labels[i], r.labels[i + 1]
+        for n in range(4):
+            dq = np.array([n & 1, n >> 1])
+            allowed = np.all(ql[:, None, :] + dq[None, None, :] == qr[None, :, :], axis=2)
+            assert np.all(T[:, n, :][~allowed] == 0)
+
+
 def test_dfci_matches_combinatorial_counts():
     assert mps.dfci_bonds(8, (3, 4))[4] == 160
     assert mps.dfci_bonds(10, (4, 5))[5] == 704
