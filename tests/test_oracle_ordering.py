@@ -138,3 +138,30 @@ def test_fiedler_order_lowers_truncation_weight():
         _, d = mps.from_full(space.embed(v[:, 0]), L, Q, Dmax=12)
         disc.append(d)
     assert disc[1] < 0.01 * disc[0]
+
+
+def test_laplacian_quadratic_form_and_courant_fischer():
+    """The identity sum_ij w_ij (x_i - x_j)^2 = 2 x^T Lap x for any x (with x the positions
+    this is the spread the ordering relaxes), Lap 1 = 0, and the variational property of the
+    Fiedler value: no unit vector orthogonal to 1 has a smaller Rayleigh quotient, and the
+    Fiedler vector is such a vector that attains it."""
+    rng = np.random.default_rng(23)
+    L = 9
+    w = np.abs(rng.standard_normal((L, L)))
+    w = w + w.T
+    np.fill_diagonal(w, 0.0)
+    lap = ordering.laplacian(w)
+    idx = np.arange(L, dtype=float)
+    assert abs(ordering.weighted_spread(w) - 2 * idx @ lap @ idx) < 1e-10 * ordering.weighted_spread(w)
+    for _ in range(5):
+        x = rng.standard_normal(L)
+        direct = sum(w[i, j] * (x[i] - x[j]) ** 2 for i in range(L) for j in range(L))
+        assert abs(direct - 2 * x @ lap @ x) < 1e-10 * direct
+    assert np.allclose(lap @ np.ones(L), 0.0, atol=1e-12)
+    lam2, v = ordering.fiedler_vector(w)
+    assert abs(v.sum()) < 1e-10 and abs(v @ v - 1) < 1e-12
+    assert abs(v @ lap @ v - lam2) < 1e-12 * lam2
+    for _ in range(200):
+        x = rng.standard_normal(L)
+        x -= x.mean()
+        assert x @ lap @ x / (x @ x) >= lam2 * (1 - 1e-12)
