@@ -270,6 +270,32 @@ def test_mps_sequential_svd_exact_and_truncation_weight():
     assert max(mt.bond_dims()) <= 12
 
 
+def test_sector_svd_against_dense_svd():
+    """Charge-sector SVD of a block-sparse matrix with interleaved row and column charges: its
+    singular values are those of a dense SVD of the whole matrix, U S Vh rebuilds it, each
+    singular vector lives on its own charge; truncated to D, it keeps the D largest values
+    over all sectors (the global rule) and reports the rest as the discarded weight."""
+    rng = np.random.default_rng(29)
+    qs = np.array([(0, 0), (1, 0), (0, 1), (1, 1)])
+    rq = qs[rng.integers(0, 4, 14)]
+    cq = qs[rng.integers(0, 3, 11)]
+    same = np.all(rq[:, None, :] == cq[None, :, :], axis=2)
+    M = np.where(same, rng.standard_normal(same.shape) + 1j * rng.standard_normal(same.shape), 0)
+    dense = np.linalg.svd(M, compute_uv=False)
+    U, S, Vh, lab, disc = mps.sector_svd(M, rq, cq, 10 ** 9, 1e-12)
+    k = len(S)
+    assert np.allclose(np.sort(S)[::-1], dense[:k], rtol=1e-12) and np.all(dense[k:] < 1e-10)
+    assert np.linalg.norm(U @ np.diag(S) @ Vh - M) < 1e-12 * np.linalg.norm(M)
+    assert np.allclose(U.conj().T @ U, np.eye(k), atol=1e-12)
+    for j in range(k):
+        assert np.all(U[~np.all(rq == lab[j], axis=1), j] == 0)
+        assert np.all(Vh[j, ~np.all(cq == lab[j], axis=1)] == 0)
+    U4, S4, Vh4, _, disc4 = mps.sector_svd(M, rq, cq, 4, 1e-12)
+    assert np.allclose(np.sort(S4)[::-1], dense[:4], rtol=1e-12)
+    assert abs(disc4 - np.sum(dense[4:] ** 2)) < 1e-10 * np.sum(dense ** 2)
+    assert abs(np.linalg.norm(U4 @ np.diag(S4) @ Vh4 - M) ** 2 - disc4) < 1e-10 * np.sum(dense ** 2)
+
+
 def test_right_canonical_form_keeps_the_state():
     """Right canonicalisation of a truncated MPS: the contracted state is unchanged, sites
     1..L-1 are right-orthonormal (sum over n, b of B B^H = 1), and every nonzero element
