@@ -199,6 +199,38 @@ def test_heff_on_determinant_basis_matches_slater_condon(ctx):
         assert abs(out[where[x]] - want) < 1e-12 * scale
 
 
+@pytest.mark.parametrize("c", [0, 1, 4, 6])
+def test_heff_off_centre_bonds_match_slater_condon(ctx, c):
+    """H_eff at the edge bonds and on both sides of the L/2 switch of the operator automaton
+    (L = 8: bonds (0,1), (1,2), (4,5), (6,7)), on determinant bond bases: sampled outputs
+    equal Slater-Condon sums over all inputs."""
+    L, D = 8, 48
+    Nu, Nd = 4, 3
+    h, eri, _ = synth.integrals(L)
+    mpo = T.MPO.from_integrals(ctx, h, eri, 0.0)
+    bonds, data, S, Tset = synth.det_basis_state(L, Nu, Nd, D, seed=5, centre=c)
+    st = T.MPS.from_blocks(ctx, bonds, data)
+    op = T.Heff(mpo, st, st, c)
+    tot, blocks = op.layout(0)
+    rng = np.random.default_rng(40 + c)
+    theta = rng.standard_normal(tot // 2) + 1j * rng.standard_normal(tot // 2)
+    tin = torch.from_numpy(theta.view(np.float64).copy()).cuda()
+    tout = torch.full_like(tin, float("nan"))
+    op.apply(tin.data_ptr(), tout.data_ptr())
+    torch.cuda.synchronize()
+    out = tout.cpu().numpy().view(np.complex128)
+    masks, where = _theta_masks(L, c, blocks, S, Tset)
+    assert 0 < len(masks) <= tot // 2
+    sc = slater.SlaterCondon(h, eri)
+    for x in rng.choice(len(masks), size=min(20, len(masks)), replace=False):
+        diff = np.bitwise_count((masks ^ masks[x]).astype(np.uint64))
+        cand = np.nonzero(diff <= 4)[0]
+        terms = np.array([sc.element(int(masks[x]), int(masks[y])) for y in cand])
+        want = np.sum(terms * theta[where[cand]])
+        scale = np.sum(np.abs(terms * theta[where[cand]])) + 1e-300
+        assert abs(out[where[x]] - want) < 1e-12 * scale
+
+
 def test_heff_full_size_sampled_outputs(ctx):
     """The benchmark's workload in the benchmark's launch configuration: centre H_eff at L = 24,
     D = 1024 (MPO bond dimension 1226, 516 blocks), replayed from a HIP graph with autotuned
