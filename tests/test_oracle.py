@@ -270,6 +270,27 @@ def test_mps_sequential_svd_exact_and_truncation_weight():
     assert max(mt.bond_dims()) <= 12
 
 
+def test_product_state_lands_on_its_fock_index():
+    """Contraction order of the MPS (site 0 most significant) against the Fock index of the
+    FCI basis: a determinant's product state is the unit vector at the base-4 number of its
+    occupation codes, that index maps back to the same spin-orbital mask in the full basis,
+    and the mask carries the determinant's electron counts."""
+    rng = np.random.default_rng(3)
+    L = 5
+    masks, _ = fci.full_basis(L)
+    for _ in range(12):
+        occ = rng.integers(0, 4, L)
+        v = mps.to_full(mps.from_occ(occ))
+        idx = int(sum(int(n) * 4 ** (L - 1 - p) for p, n in enumerate(occ)))
+        assert np.count_nonzero(v) == 1 and v[idx] == 1
+        m = fci.mask_from_occ(occ)
+        assert int(fci.fock_index(np.array([m]), L)[0]) == idx and int(masks[idx]) == m
+        n_up = sum(int(n) & 1 for n in occ)
+        n_dn = sum(int(n) >> 1 for n in occ)
+        assert bin(m & int("01" * L, 2)).count("1") == n_up
+        assert bin(m & int("10" * L, 2)).count("1") == n_dn
+
+
 def test_sector_svd_against_dense_svd():
     """Charge-sector SVD of a block-sparse matrix with interleaved row and column charges: its
     singular values are those of a dense SVD of the whole matrix, U S Vh rebuilds it, each
