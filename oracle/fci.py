@@ -204,6 +204,9 @@ class HamiltonianOp:
         self.dtype = np.complex128
 
     def matvec(self, v):
+        v = np.asarray(v)
+        if v.ndim == 2:  # a block of vectors, column by column
+            return np.stack([self.matvec(v[:, j]) for j in range(v.shape[1])], axis=1)
         L = self.L
         w = np.stack([self.E[q, s] @ v for q in range(L) for s in range(L)])  # (L^2, dim)
         u = self.eri.reshape(L * L, L * L) @ w                                  # (L^2, dim)

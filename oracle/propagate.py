@@ -19,14 +19,43 @@ import scipy.linalg as sla
 import scipy.sparse.linalg as spla
 
 
-def exact(H, psi, t):
-    """exp(-i H t) psi: dense eigh up to dimension 6000, scipy's expm_multiply beyond."""
-    if isinstance(H, np.ndarray) or H.shape[0] <= 6000:
+def exact(H, psi, t, method="auto"):
+    """exp(-i H t) psi (Eq. (time_evo_opera)).
+
+    method "eigh": spectral decomposition of the dense H; "expm": scipy's expm_multiply
+    (truncated Taylor series with scaling, for sectors too large for eigh; H may then be a
+    matrix-free operator with H @ v); "auto": eigh up to dimension 6000, expm beyond."""
+    dense_ok = isinstance(H, np.ndarray) or hasattr(H, "toarray")
+    if method == "auto":
+        method = "eigh" if dense_ok and H.shape[0] <= 6000 else "expm"
+    if method == "eigh":
         Hd = H if isinstance(H, np.ndarray) else H.toarray()
         w, V = np.linalg.eigh(Hd)
         return V @ (np.exp(-1j * w * t) * (V.conj().T @ psi))
-    A = spla.LinearOperator(H.shape, matvec=lambda v: -1j * t * (H @ v), dtype=np.complex128)
+    if method != "expm":
+        raise ValueError(f"unknown method {method}")
+    # scipy's norm estimate also applies the adjoint, (-i t H)^H = +i t H for Hermitian H
+    A = spla.LinearOperator(H.shape, matvec=lambda v: -1j * t * (H @ v), rmatvec=lambda v: 1j * t * (H @ v),
+                            dtype=np.complex128)
     return spla.expm_multiply(A, np.asarray(psi, dtype=np.complex128), traceA=0.0)
+
+
+def free_fermion_one_rdm(h, occ, t):
+    """Spin-summed gamma_pq(t) = sum_s <a+_{ps} a_{qs}> for V = 0 and a determinant start.
+
+    With V = 0 each electron moves under the one-body h alone: a_{qs}(t) = sum_r U_qr a_{rs}
+    with U = exp(-i h t), so <a+_{ps}(t) a_{qs}(t)> = sum_{rr'} conj(U_pr) U_qr' <a+_{rs} a_{r's}>
+    and gamma(t) = conj(U) gamma(0) U^T with gamma(0) = diag(n_p) for the determinant with
+    occupation codes occ (n_p = number of electrons in orbital p).  Holds at any L."""
+    w, V = np.linalg.eigh(np.asarray(h, dtype=np.float64))
+    U = (V * np.exp(-1j * w * t)) @ V.conj().T
+    n = np.array([(int(o) & 1) + ((int(o) >> 1) & 1) for o in occ], dtype=np.float64)
+    return U.conj() @ np.diag(n) @ U.T
+
+
+def free_fermion_dipole(h, mu, occ, t):
+    """<mu>(t) = sum_pq mu_pq gamma_pq(t) for V = 0 (the closed form of free_fermion_one_rdm)."""
+    return float(np.real(np.sum(np.asarray(mu) * free_fermion_one_rdm(h, occ, t))))
 
 
 def rk4(Hmv, psi, dt, t=0.0):

@@ -95,7 +95,10 @@ def test_one_electron_reduces_to_h():
 
 
 def test_free_fermion_dipole_closed_form():
-    """V = 0: rho_sigma(t) = exp(-iht) rho(0) exp(iht), <mu>(t) = sum_sigma Tr(mu rho)."""
+    """V = 0: rho_sigma(t) = exp(-iht) rho(0) exp(iht), <mu>(t) = sum_sigma Tr(mu rho); the
+    oracle's closed forms (free_fermion_one_rdm / free_fermion_dipole, used at L = 16 and 24
+    where no dense propagation exists) equal the many-body propagation on the FCI sector, and
+    the spin-resolved trace written out here."""
     L = 6
     h, _ = synth.integrals(L)[:2]
     mu = synth.dipole_matrix(L)
@@ -107,7 +110,7 @@ def test_free_fermion_dipole_closed_form():
     psi0 = np.zeros(space.dim, complex)
     psi0[space.lookup(fci.mask_from_occ(occ))[0]] = 1
     w, V = np.linalg.eigh(h)
-    for t in (0.0, 0.3, 1.7):
+    for t in (0.0, 0.3, 1.7, -0.4):
         psi = propagate.exact(H, psi0, t)
         got = fci.expectation(M, psi).real
         U = V @ np.diag(np.exp(-1j * w * t)) @ V.conj().T
@@ -116,6 +119,49 @@ def test_free_fermion_dipole_closed_form():
             rho0 = np.diag([(int(o) & s) > 0 for o in occ]).astype(float)
             want += np.trace(mu @ (U @ rho0 @ U.conj().T)).real
         assert abs(got - want) < 1e-11
+        assert abs(propagate.free_fermion_dipole(h, mu, occ, t) - got) < 1e-11
+        g = fci.one_rdm(space, psi)
+        assert np.abs(propagate.free_fermion_one_rdm(h, occ, t) - g).max() < 1e-11
+    # the sign of the time matters: gamma(t) and gamma(-t) differ (imaginary parts flip)
+    g1, g2 = propagate.free_fermion_one_rdm(h, occ, 0.3), propagate.free_fermion_one_rdm(h, occ, -0.3)
+    assert np.abs(g1.imag).max() > 1e-3 and np.abs(g1 - g2.conj()).max() < 1e-14
+
+
+@pytest.mark.parametrize("L", [6, 8])
+def test_matrix_free_hamiltonian_equals_assembled(L):
+    """fci.HamiltonianOp (used where the sector is too large to assemble, L = 10) against the
+    assembled sparse Hamiltonian, itself pinned to term-by-term brute force, on random complex
+    vectors; with e0 and two different sectors."""
+    h, eri = _rand_integrals(L, 30 + L)
+    rng = np.random.default_rng(L)
+    for nu, nd in ((L // 2, L // 2 - 1), (2, 3)):
+        space = fci.Space.sector(L, nu, nd)
+        H = fci.hamiltonian(space, h, eri, 0.7)
+        op = fci.HamiltonianOp(space, h, eri, 0.7)
+        v = rng.standard_normal(space.dim) + 1j * rng.standard_normal(space.dim)
+        want = H @ v
+        assert np.abs(op @ v - want).max() < 1e-13 * np.abs(want).max()
+
+
+def test_exact_propagator_expm_branch_equals_eigh():
+    """The expm_multiply branch of propagate.exact (taken above dimension 6000, and with a
+    matrix-free operator) against the spectral decomposition on the L = 8, N = 7 sector
+    (dimension 3920), forward and backward in time; unitarity of both."""
+    L = 8
+    h, eri, _ = synth.integrals(L)
+    occ = synth.ionized_determinant(L, 8)
+    space = fci.Space.sector(L, *synth.occ_charge(occ))
+    H = fci.hamiltonian(space, h, eri)
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal(space.dim) + 1j * rng.standard_normal(space.dim)
+    v /= np.linalg.norm(v)
+    for t in (0.05, 0.7, -0.3):
+        a = propagate.exact(H, v, t, method="eigh")
+        b = propagate.exact(H, v, t, method="expm")
+        c = propagate.exact(fci.HamiltonianOp(space, h, eri), v, t)  # matrix-free: expm branch
+        assert np.abs(a - b).max() < 1e-10
+        assert np.abs(a - c).max() < 1e-10
+        assert abs(np.linalg.norm(b) - 1) < 1e-11
 
 
 def test_one_rdm_pins():
