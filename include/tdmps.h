@@ -107,12 +107,14 @@ tdmps_status tdmps_ctx_destroy(tdmps_ctx ctx);
  * preconditioning, out[16] = host seconds spent building GEMM plans (included in the H_eff
  * and environment times), out[17] / out[18] = device allocations the caching allocator has
  * made so far in the process and the seconds spent in them, out[19] = premix structures built
- * so far in the process (misses of the cache of per-site coefficient matrices).  After
+ * so far in the process (misses of the cache of per-site coefficient matrices), out[20] =
+ * weight discarded by the truncations of the last sweep of every fit of the operation, summed
+ * over the fits (the squared-norm error the SVD truncations introduced).  After
  * tdmps_heff_apply planning, out[0..9] describe the plan instead: algorithmic flops, executed
  * flops of the two stages, bytes of the intermediate, task and segment counts of the two
  * stages, the number of shared-environment runs (channels of one environment block with
  * their own coefficients, summed by the share pass) and the bytes of their products. */
-#define TDMPS_NCOUNTERS 20
+#define TDMPS_NCOUNTERS 21
 tdmps_status tdmps_ctx_counters(tdmps_ctx ctx, double* out);
 tdmps_status tdmps_ctx_reset_counters(tdmps_ctx ctx);
 /* Launch mode of tdmps_heff_apply (Batching row of the benchmark set): 1 = every block product
@@ -149,6 +151,14 @@ tdmps_status tdmps_ctx_clear_tuning(tdmps_ctx ctx);
  *   + 1/2 sum_pqrs (pr|qs) a+_{p s} a+_{q t} a_{s t} a_{r s} + e0,
  * i.e. V_ijkl = (ik|jl) from chemists' integrals.  h: L*L row-major symmetric; eri: L^4
  * row-major (pq|rs) with 8-fold symmetry.  Returns TDMPS_ERR_NUMERIC for NaN/Inf input.
+ * Channels: identity, complete, one open operator (with its complementary three-operator sum),
+ * and pairs of operators named by the smaller side of the cut; at the cuts within L/6 of the
+ * chain centre (environment variable TDMPS_MPO_ROUTING_WINDOW: another distance, -1 none) a
+ * pair whose opposite operator sits on the site next to the cut is named by the other side, so
+ * every complementary crossing of a pair happens on a site without operators of the term.
+ * tdmps_mpo_bond_dims reports the channels as built; with the plain rule (-1) the bond
+ * dimension at the centre is 2L^2 + 3L + 2.  Algorithmic flop counts always refer to the
+ * plain rule.
  * ctx may be NULL for a host-only operator (tdmps_mpo_to_dense, tdmps_mpo_det_element). */
 tdmps_status tdmps_mpo_from_integrals(tdmps_ctx ctx, int32_t L, const double* h, const double* eri,
                                       double e0, tdmps_mpo* out);
@@ -187,6 +197,27 @@ tdmps_status tdmps_mps_sectors(tdmps_mps mps, int32_t* bond_nsec, int32_t* bond_
 tdmps_status tdmps_mps_get_blocks(tdmps_mps mps, double* data, int64_t* len);
 /* Dense 4^L coefficient vector (interleaved complex, len = 2*4^L; L <= 12). */
 tdmps_status tdmps_mps_to_dense(tdmps_mps mps, double* out, int64_t len);
+/* State of a dense vector (tiny L only, 2 <= L <= 12) by the sequential SVD of the MPS
+ * section of Methods (Eq. (mps)): split off one site after another from the left, keeping
+ * at most Dmax singular values per bond (global descending order over the charge sectors of
+ * the bond) and none at or below svd_cutoff * sigma_max; nothing is renormalised.
+ *   coeffs : 4^L interleaved complex coefficients in the dense order of tdmps_mps_to_dense
+ *            (len = 2*4^L doubles), all zero outside the sector of N electrons with
+ *            2Sz = N_up - N_dn (else TDMPS_ERR_SECTOR); copied, not retained.
+ * The result has bond dimensions <= Dmax (the exact state when Dmax >= D_FCI).
+ * TDMPS_ERR_NUMERIC for NaN/Inf coefficients. */
+tdmps_status tdmps_mps_from_dense(tdmps_ctx ctx, int32_t L, int32_t N, int32_t twoSz, const double* coeffs,
+                                  int64_t len, int32_t Dmax, double svd_cutoff, tdmps_mps* out);
+/* Checkpoint files (for resuming a time evolution).  tdmps_mps_save writes the state to
+ * path: an 8-byte magic "TDMPSv1\0", int32 L, N_up, N_dn, 0, then per bond int32 count and
+ * count x (int32 n_up, n_dn, dim), then per site int64 n and n interleaved complex FP64 values
+ * in the panel layout, then a 64-bit FNV-1a checksum of everything before it (little
+ * endian).  tdmps_mps_load reads such a file into a new state on ctx: the same bonds and the
+ * same bits, so a run continued from it is bitwise the run that was saved.  TDMPS_ERR_ARG for
+ * unreadable, truncated, inconsistent or corrupt files (checksum), TDMPS_ERR_NUMERIC for
+ * non-finite values. */
+tdmps_status tdmps_mps_save(tdmps_mps mps, const char* path);
+tdmps_status tdmps_mps_load(tdmps_ctx ctx, const char* path, tdmps_mps* out);
 tdmps_status tdmps_mps_copy(tdmps_mps mps, tdmps_mps* out);
 tdmps_status tdmps_mps_bond_dims(tdmps_mps mps, int32_t* out);
 tdmps_status tdmps_mps_destroy(tdmps_mps mps);
@@ -279,8 +310,11 @@ tdmps_status tdmps_heff_destroy(tdmps_heff op);
  * discrete RK4 map: the states between checkpoints are recomputed and the adjoint stages
  * are propagated backwards with the same fit / H_eff / environment kernels (H Hermitian, so
  * the adjoint of an H application is an H application with -i dt -> +i dt).  At full bond
- * dimension the result is the exact derivative of the discrete map; with truncation it is
- * the derivative with the truncations held fixed.
+ * dimension (every fit exact and converged) the result is the exact derivative of the discrete
+ * map.  Below it the adjoint stage maps are applied by fits of their own, each truncated to
+ * Dmax: the result then approximates the derivative of the truncated forward map, with an
+ * error of the order of the truncation (it does not differentiate the choice of the kept
+ * singular vectors).
  *   H0       : MPO of H0 (its one-body part is replaced by h0 + E(t) m at every stage time).
  *   h0, m    : L*L row-major one-body integrals of H0 and of the field coupling.
  *   mu       : observable MPO (e.g. tdmps_mpo_one_body of the dipole integrals).

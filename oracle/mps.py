@@ -157,6 +157,7 @@ def from_full(vec, L, Q, Dmax=10 ** 9, cutoff=1e-12):
         rq = (labels[i][:, None, :] + QLOC[None, :, :]).reshape(-1, 2)
         cq = Q[None, :] - _config_charges(L - i - 1)
         U, S, Vh, lab, d = sector_svd(M, rq, cq, Dmax, cutoff)
+        GAP_LOG.append(LAST_GAP[0])
         disc += d
         k = len(S)
         tensors.append(U.reshape(Dl, 4, k))
@@ -204,21 +205,28 @@ def _right_basis(m: MPS, i):
     return v  # (D_i, 4^(L-i))
 
 
-def fit(target, init: MPS, Dmax, n_sweeps=2, cutoff=1e-12, conv_tol=0.0):
-    """Two-site variational fit of a dense target (replica of the local solves)."""
+def fit(target, init: MPS, Dmax, n_sweeps=2, cutoff=1e-12, conv_tol=0.0, first_pass_target=None):
+    """Two-site variational fit of a dense target (replica of the local solves).
+
+    first_pass_target: if given, the first left-to-right pass projects this vector instead of
+    the target (the initial guess of the orthogonal Krylov fits, reading c8 of the design
+    notes: a target orthogonal to the guess has no projection on a product-state guess's
+    bases, so the bases are first grown on H phi_k, which contains the guess)."""
     L = init.L
     C = right_canonicalize(init, cutoff)
     info = FitInfo()
     T = np.asarray(target, dtype=np.complex128)
+    T0 = T if first_pass_target is None else np.asarray(first_pass_target, dtype=np.complex128)
     prev = None
     for sweep in range(n_sweeps):
         last_norm = 0.0
         for direction, bonds in (("lr", range(0, L - 1)), ("rl", range(L - 2, -1, -1))):
+            src = T0 if (sweep == 0 and direction == "lr") else T
             for i in bonds:
                 Lb = _left_basis(C, i)
                 Rb = _right_basis(C, i + 2)
                 Dl, Dr = Lb.shape[1], Rb.shape[0]
-                Tm = T.reshape(4 ** i, 16, 4 ** (L - i - 2))
+                Tm = src.reshape(4 ** i, 16, 4 ** (L - i - 2))
                 theta = np.einsum("xa,xsy,by->asb", Lb.conj(), Tm, Rb.conj(), optimize=True)
                 M = theta.reshape(Dl * 4, 4 * Dr)
                 rq = (C.labels[i][:, None, :] + QLOC[None, :, :]).reshape(-1, 2)
@@ -263,12 +271,15 @@ class DenseOps:
         self.H = Hfull
         self.Dmax, self.n_sweeps, self.cutoff = Dmax, n_sweeps, cutoff
 
-    def apply_H(self, alpha, psi: MPS, terms=(), H=None):
+    def apply_H(self, alpha, psi: MPS, terms=(), H=None, grow_on_H=False):
+        """Fit of alpha H psi + sum_j beta_j phi_j from psi; grow_on_H: the first left-to-right
+        pass fits alpha H psi alone (the orthogonal Krylov vectors, reading c8)."""
         H = self.H if H is None else H
-        t = alpha * H(to_full(psi))
+        h = alpha * H(to_full(psi))
+        t = h
         for beta, phi in terms:
             t = t + beta * to_full(phi)
-        return fit(t, psi, self.Dmax, self.n_sweeps, self.cutoff)[0]
+        return fit(t, psi, self.Dmax, self.n_sweeps, self.cutoff, first_pass_target=h if grow_on_H else None)[0]
 
     def compress(self, terms):
         t = sum(beta * to_full(phi) for beta, phi in terms)
@@ -308,7 +319,7 @@ class DenseOps:
             terms = []
             if orthogonal:
                 terms = [(-Hm[j, k] / Nm[j, j], phis[j]) for j in range(k + 1)]
-            nxt = self.apply_H(1.0, phis[k], terms)
+            nxt = self.apply_H(1.0, phis[k], terms, grow_on_H=orthogonal)
             nrm = np.sqrt(overlap(nxt, nxt).real)
             nxt = scale(nxt, 1.0 / nrm)
             phis.append(nxt)

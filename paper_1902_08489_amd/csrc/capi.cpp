@@ -6,6 +6,7 @@
 #include <memory>
 
 #include "drivers.h"
+#include "io.h"
 #include "pulse.h"
 #include "engine.h"
 
@@ -61,6 +62,7 @@ void publish(Ctx* ctx, const Contractor& C) {
   ctx->counters[16] = C.t_plan;
   dev_alloc_stats(&ctx->counters[17], &ctx->counters[18]);
   ctx->counters[19] = tdmps::premix_structures_built();
+  ctx->counters[20] = C.fit_discarded;
 }
 
 void check_prm(const tdmps_fit_params* p) {
@@ -329,6 +331,41 @@ extern "C" tdmps_status tdmps_mps_bond_dims(tdmps_mps m, int32_t* out) {
   return guard([&] {
     TDMPS_REQUIRE(m && out, TDMPS_ERR_ARG, "NULL argument");
     for (int i = 0; i <= m->L; ++i) out[i] = m->bond[i].total();
+  });
+}
+
+extern "C" tdmps_status tdmps_mps_from_dense(tdmps_ctx ctx, int32_t L, int32_t N, int32_t twoSz, const double* coeffs,
+                                             int64_t len, int32_t Dmax, double svd_cutoff, tdmps_mps* out) {
+  return guard([&] {
+    TDMPS_REQUIRE(ctx && coeffs && out, TDMPS_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    TDMPS_REQUIRE(L >= 2 && L <= 12, TDMPS_ERR_ARG, "from_dense supports 2 <= L <= 12");
+    int64_t full = 1;
+    for (int i = 0; i < L; ++i) full *= 4;
+    TDMPS_REQUIRE(len == 2 * full, TDMPS_ERR_ARG, "len must be 2*4^L");
+    TDMPS_REQUIRE(((N + twoSz) & 1) == 0 && N >= 0 && std::abs(twoSz) <= N, TDMPS_ERR_SECTOR,
+                  "N and 2Sz must have equal parity with |2Sz| <= N");
+    TDMPS_REQUIRE(svd_cutoff >= 0 && std::isfinite(svd_cutoff), TDMPS_ERR_ARG, "bad svd_cutoff");
+    tdmps_fit_params prm{};
+    Contractor C = make_contractor(ctx, &prm);
+    *out = mps_from_dense(C, L, Charge((N + twoSz) / 2, (N - twoSz) / 2), coeffs, Dmax, svd_cutoff);
+  });
+}
+
+extern "C" tdmps_status tdmps_mps_save(tdmps_mps m, const char* path) {
+  return guard([&] {
+    TDMPS_REQUIRE(m && path, TDMPS_ERR_ARG, "NULL argument");
+    dev_bind(m->ctx->device, m->ctx->stream);
+    mps_save(m, path);
+  });
+}
+
+extern "C" tdmps_status tdmps_mps_load(tdmps_ctx ctx, const char* path, tdmps_mps* out) {
+  return guard([&] {
+    TDMPS_REQUIRE(ctx && path && out, TDMPS_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    dev_bind(ctx->device, ctx->stream);
+    *out = mps_load(ctx, path);
   });
 }
 

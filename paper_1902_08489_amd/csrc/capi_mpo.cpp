@@ -1,4 +1,5 @@
 // C ABI: errors and the Hamiltonian MPO entry points.
+#include <cstdlib>
 #include <cstring>
 
 #include "engine.h"
@@ -23,7 +24,12 @@ extern "C" tdmps_status tdmps_mpo_from_integrals(tdmps_ctx ctx, int32_t L, const
     auto* m = new tdmps_mpo_s();
     try {
       m->ctx = ctx;
-      m->host = build_mpo(L, h, eri, e0, true);
+      // pair-channel routing window (the adjacent-operator rule of mpo.cpp): L/6 cuts on each
+      // side of the centre (the lowest D^3-weighted pattern count of a sweep at L = 16..30);
+      // TDMPS_MPO_ROUTING_WINDOW overrides it, -1 gives the plain rule everywhere
+      int window = L / 6;
+      if (const char* e = std::getenv("TDMPS_MPO_ROUTING_WINDOW")) window = std::atoi(e);
+      m->host = build_mpo(L, h, eri, e0, true, window);
     } catch (...) {
       delete m;
       throw;

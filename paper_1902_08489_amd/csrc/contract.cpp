@@ -210,6 +210,7 @@ SideOps build_ops(Contractor& C, const Env& E, const MpoHost& W, int site, bool 
   SideOps ops;
   ops.cut = left ? site + 1 : site;
   ops.env = &E;
+  if ((int)W.plain_cls.size() > E.cut && !W.plain_cls[E.cut].empty()) ops.ref_cls = &W.plain_cls[E.cut];
   if (!sk->groups.empty()) {
     ops.mix.reset(new Blocks());
     ops.mix->layout(E.b.bra, E.b.ket, sk->groups);
@@ -888,28 +889,33 @@ std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const Si
   }
   double alg = 0;
   // algorithmic count in the plain order (L theta) -> W -> (. R): every channel of the outer
-  // cuts against every compatible block.
+  // cuts against every compatible block, with the channels of the plain operator rule (the
+  // smallest operator; the routing of pair channels changes the executed work, not this count)
   {
-    const Blocks& Lb = lops.env->b;
-    const Blocks& Rb = rops.env->b;
-    for (const auto& g : Lb.grp)
+    auto classes = [](const SideOps& o) {
+      if (o.ref_cls) return *o.ref_cls;
+      std::vector<std::pair<Charge, int>> c;
+      for (const auto& g : o.env->b.grp) c.push_back({g.q, g.n});
+      return c;
+    };
+    for (const auto& g : classes(lops))
       for (int sk = 0; sk < ket_l.nsec(); ++sk) {
-        int sb = g.bra_of[sk];
+        const int sb = bra_l.find(ket_l.q[sk] + g.first);
         if (sb < 0) continue;
         for (int sig = 0; sig < 16; ++sig) {
           int tk = kl.rs[sk][sig];
           if (tk < 0) continue;
-          alg += 8.0 * g.n * bra_l.dim[sb] * (double)ket_l.dim[sk] * ket_r.dim[tk];
+          alg += 8.0 * g.second * bra_l.dim[sb] * (double)ket_l.dim[sk] * ket_r.dim[tk];
         }
       }
-    for (const auto& g : Rb.grp)
+    for (const auto& g : classes(rops))
       for (int s = 0; s < bra_l.nsec(); ++s)
         for (int sig = 0; sig < 16; ++sig) {
           int tb = bl.rs[s][sig];
           if (tb < 0) continue;
-          int tk = g.ket_of[tb];
+          const int tk = ket_r.find(bra_r.q[tb] - g.first);
           if (tk < 0) continue;
-          alg += 8.0 * g.n * bra_l.dim[s] * (double)bra_r.dim[tb] * ket_r.dim[tk];
+          alg += 8.0 * g.second * bra_l.dim[s] * (double)bra_r.dim[tb] * ket_r.dim[tk];
         }
     plan->alg_flops = alg;
   }

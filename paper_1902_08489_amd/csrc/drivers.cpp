@@ -258,7 +258,9 @@ static KrylovBasis krylov_basis(Contractor& C, const MpoHost* H, const Mps* psi,
         terms.push_back({cplx{b.real(), b.imag()}, phi[j].get()});
       }
     FitOut fo;
-    std::unique_ptr<Mps> nxt(fit(C, H, cplx{1, 0}, phi[k].get(), terms, prm, &fo));
+    // the orthogonalised target has no overlap with the guess phi_k: grow the bases on H phi_k
+    // first (the first left-to-right pass), then fit the whole target
+    std::unique_ptr<Mps> nxt(fit(C, H, cplx{1, 0}, phi[k].get(), terms, prm, &fo, orthogonal));
     if (progress)
       std::fprintf(stderr, "krylov: vector %d of %d after %.1f s\n", k + 1, m - 1, wall_seconds() - t_start);
     double nn = overlap(C, nxt.get(), nxt.get()).x;

@@ -211,6 +211,9 @@ struct SideOps {
   std::vector<ChanOps> ch;
   std::unique_ptr<Blocks> mix;
   std::shared_ptr<DevBuf> wmat;  // premix coefficients (device), alive until the premix plan ran
+  // (charge, count) channel classes of the environment's cut under the plain operator rule
+  // (MpoHost::plain_cls), for the algorithmic flop count; null: the environment's own classes
+  const std::vector<std::pair<Charge, int>>* ref_cls = nullptr;
 };
 
 // ---------------------------------------------------------------- GEMM plans
@@ -283,6 +286,7 @@ struct Contractor {
   double t_heff = 0, t_env = 0, t_mix = 0, t_svd = 0, t_sandwich = 0, t_qr = 0;
   double svd_sweeps = 0, svd_rounds = 0, n_svd = 0, n_heff = 0, n_env = 0, n_sandwich = 0;
   double t_plan = 0;  // host seconds building and finalising GEMM plans (H_eff and environments)
+  double fit_discarded = 0;  // sum over the fits of the weight discarded in their last sweep
 };
 
 double wall_seconds();
@@ -365,8 +369,9 @@ struct FitOut {
   std::vector<cplx> term_overlaps;
 };
 // out ~ alpha * H psi + sum_j beta_j phi_j  (H may be null: compression only)
+// grow_on_h: the first left-to-right pass fits alpha H psi alone (orthogonal Krylov vectors)
 Mps* fit(Contractor& C, const MpoHost* H, cplx alpha, const Mps* psi, const std::vector<FitTerm>& terms,
-         const tdmps_fit_params& prm, FitOut* info);
+         const tdmps_fit_params& prm, FitOut* info, bool grow_on_h = false);
 
 void scale_mps(Ctx* ctx, Mps* m, cplx alpha);
 cplx overlap(Contractor& C, const Mps* a, const Mps* b);

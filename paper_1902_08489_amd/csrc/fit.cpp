@@ -6,7 +6,9 @@
 //   theta_C = alpha H_eff theta_psi + sum_j beta_j L^{C phi_j} theta_phi_j R^{C phi_j},
 // which is then truncated by SVD and split.  A sweep is a left-to-right pass over the
 // bonds followed by a right-to-left pass.  The initial guess is the first operand,
-// right-canonicalised.
+// right-canonicalised.  With grow_on_h the first left-to-right pass projects alpha H psi
+// alone: a target orthogonal to psi (the orthogonal Krylov vectors) has no projection on the
+// bases of a product-state guess, so the bases are first grown on H psi, which contains psi.
 #include <algorithm>
 #include <cmath>
 #include <memory>
@@ -41,7 +43,7 @@ Env build_right(Contractor& C, const MpoHost& O, const Env& E, int i, const Mps*
 }  // namespace
 
 Mps* fit(Contractor& C, const MpoHost* H, cplx alpha, const Mps* psi, const std::vector<FitTerm>& terms,
-         const tdmps_fit_params& prm, FitOut* info) {
+         const tdmps_fit_params& prm, FitOut* info, bool grow_on_h) {
   TDMPS_REQUIRE(H || !terms.empty(), TDMPS_ERR_ARG, "nothing to fit");
   const Mps* first = H ? psi : terms[0].phi;
   const int L = first->L;
@@ -84,8 +86,13 @@ Mps* fit(Contractor& C, const MpoHost* H, cplx alpha, const Mps* psi, const std:
         const bool last_bond = dir == 1 && i == 0;
         std::vector<std::vector<cplx>> local(last_bond ? T.size() : 0);
         bool first_term = true;
+        const bool h_only = grow_on_h && H && sweep == 0 && dir == 0;
         for (size_t k = 0; k < T.size(); ++k) {
           Term& t = T[k];
+          if (h_only && k > 0) {  // left environment of the term still advances with the sweep
+            lkeep[k] = std::make_unique<SideOps>(premix_left(C, *t.Lenv[i], *t.op, i));
+            continue;
+          }
           TwoLayout kl;
           kl.build(t.ket->bond[i], t.ket->bond[i + 2]);
           DevBuf tin(std::max<int64_t>(kl.size, 1) * sizeof(cplx));
@@ -155,6 +162,7 @@ Mps* fit(Contractor& C, const MpoHost* H, cplx alpha, const Mps* psi, const std:
       break;
     prev = last_norm;
   }
+  C.fit_discarded += out.disc_sum;
   if (info) *info = out;
   return Cm.release();
 }

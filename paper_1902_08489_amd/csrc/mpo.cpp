@@ -124,7 +124,9 @@ struct TransHash {
 
 struct Builder {
   int L, K, imid;
+  int adjacent_window = -1;  // cuts i with |i - imid| <= window use the adjacent-operator rule
   std::unordered_map<uint64_t, std::pair<int, int>> range;  // key -> [first cut, last cut]
+  std::unordered_map<uint64_t, std::pair<int, int>> range_plain;  // the same under the plain rule
   std::unordered_map<TransKey, Mat4, TransHash> structural;
   std::unordered_map<TransKey, Mat4, TransHash> coeff;      // from two-body terms and e0
   struct OB {
@@ -134,7 +136,7 @@ struct Builder {
   };
   std::vector<OB> onebody;
 
-  void touch(uint64_t k, int a, int b) {
+  static void touch_in(std::unordered_map<uint64_t, std::pair<int, int>>& range, uint64_t k, int a, int b) {
     auto it = range.find(k);
     if (it == range.end())
       range.emplace(k, std::make_pair(a, b));
@@ -142,7 +144,8 @@ struct Builder {
       it->second.first = std::min(it->second.first, a);
       it->second.second = std::max(it->second.second, b);
     }
-  }
+  }  void touch(uint64_t k, int a, int b) { touch_in(range, k, a, b); }
+
 
   // ops in written order; one-body terms carry (p, q) so their coefficient can be replaced.
   void term(double coef, std::vector<SOp> ops, int obp, int obq) {
@@ -174,7 +177,7 @@ struct Builder {
         if (o.so < c) s += o.f;
       return s;
     };
-    auto key_at = [&](int i) -> uint64_t {
+    auto key_at = [&](int i, int window) -> uint64_t {
       int c = 2 * i;
       int nl = nl_at(c);
       if (nl == 0) return mk_key(K_I, 0, 0);
@@ -183,11 +186,44 @@ struct Builder {
       for (auto& o : m) (o.so < c ? lo : ro).push_back(opcode(o));
       if (nl == 1) return mk_key(K_L1, lo[0], 0);
       if (nl == 3) return mk_key(K_R1, ro[0], 0);
-      if (i < imid) return mk_key(K_L2, lo[0], lo.size() > 1 ? lo[1] : 0);
+      // two operators on each side: name the pair of the left side (L2) left of the chain
+      // centre and that of the right side (R2) right of it, except when the operator nearest
+      // to the cut on the named side's opposite side sits on the site next to the cut.  Then
+      // the other pair is named, so that the transition on that site is a pure operator and
+      // every coefficient crossing of a pair channel happens on a site without operators of
+      // the term (all its channels combine the same four diagonal matrix units).
+      int last_left = -1, first_right = L;
+      for (auto& o : m) {
+        const int site = o.so >> 1;
+        if (o.so < c) last_left = std::max(last_left, site);
+        else first_right = std::min(first_right, site);
+      }
+      bool left_pair = i < imid;
+      if (std::abs(i - imid) <= window) left_pair = i < imid ? first_right != i : last_left == i - 1;
+      if (left_pair) return mk_key(K_L2, lo[0], lo.size() > 1 ? lo[1] : 0);
       return mk_key(K_R2, ro[0], ro.size() > 1 ? ro[1] : 0);
     };
     std::vector<uint64_t> keys(L + 1);
-    for (int i = 0; i <= L; ++i) keys[i] = key_at(i);
+    for (int i = 0; i <= L; ++i) keys[i] = key_at(i, adjacent_window);
+    // channels of the plain rule (the smallest MPO, 2L^2 + 3L + 2 at the centre): the reference
+    // of the algorithmic flop count
+    if (adjacent_window >= 0) {
+      uint64_t prev = key_at(0, -1);
+      int first = 0;
+      for (int i = 1; i <= L + 1; ++i) {
+        const uint64_t k = i <= L ? key_at(i, -1) : ~0ull;
+        if (k != prev) {
+          touch_in(range_plain, prev, first, i - 1);
+          prev = k;
+          first = i;
+        }
+      }
+    }
+    // a term crosses from the left-unique channels (I, L1, L2) to the right-unique ones exactly
+    // once, where its coefficient sits
+    for (int i = 0; i < L; ++i)
+      TDMPS_REQUIRE(left_unique(key_type(keys[i])) || !left_unique(key_type(keys[i + 1])), TDMPS_ERR_NUMERIC,
+                    "internal: operator automaton returns to a left-unique channel");
     int start = 0;
     for (int i = 1; i <= L + 1; ++i) {
       if (i == L + 1 || keys[i] != keys[start]) {
@@ -240,7 +276,7 @@ int mpo_channel_kind(uint64_t key, int* so, int* op) {
   return 3;
 }
 
-MpoHost build_mpo(int L, const double* h, const double* eri, double e0, bool two_body) {
+MpoHost build_mpo(int L, const double* h, const double* eri, double e0, bool two_body, int adjacent_window) {
   TDMPS_REQUIRE(L >= 2 && L <= 64, TDMPS_ERR_ARG, "L must be in [2, 64]");
   for (int64_t i = 0; i < (int64_t)L * L; ++i)
     TDMPS_REQUIRE(std::isfinite(h[i]), TDMPS_ERR_NUMERIC, "non-finite one-body integral");
@@ -253,6 +289,7 @@ MpoHost build_mpo(int L, const double* h, const double* eri, double e0, bool two
   b.L = L;
   b.K = 2 * L;
   b.imid = L / 2;
+  b.adjacent_window = adjacent_window;
   // one-body terms: every (p, q, spin) is laid down so that set_one_body can change h
   for (int p = 0; p < L; ++p)
     for (int q = 0; q < L; ++q)
@@ -289,6 +326,14 @@ MpoHost build_mpo(int L, const double* h, const double* eri, double e0, bool two
   MpoHost M;
   M.L = L;
   M.cut.resize(L + 1);
+  M.plain_cls.resize(L + 1);
+  if (adjacent_window >= 0) {
+    std::vector<std::map<Charge, int>> cnt(L + 1);
+    for (auto& kv : b.range_plain)
+      for (int c = kv.second.first; c <= kv.second.second; ++c) cnt[c][key_charge(kv.first)]++;
+    for (int c = 0; c <= L; ++c)
+      for (auto& kv : cnt[c]) M.plain_cls[c].push_back(kv);
+  }
   std::vector<std::unordered_map<uint64_t, int>> index(L + 1);
   std::vector<std::vector<uint64_t>> alive(L + 1);
   for (auto& kv : b.range)
@@ -314,6 +359,8 @@ MpoHost build_mpo(int L, const double* h, const double* eri, double e0, bool two
       cu.cls_count.back()++;
       cu.cls_of.push_back((int)cu.cls_q.size() - 1);
     }
+    if (adjacent_window < 0)
+      for (size_t k = 0; k < cu.cls_q.size(); ++k) M.plain_cls[c].push_back({cu.cls_q[k], cu.cls_count[k]});
   }
 
   // assemble per-site transitions: structural + pass-through + coefficient sums

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <array>
+#include <utility>
 
 #include "common.h"
 
@@ -46,12 +47,18 @@ struct MpoHost {
   std::vector<std::vector<double>> c_fixed;  // part of each coefficient not from h
   std::vector<OneBodyRef> onebody;           // linear dependence of coefficients on h
   std::vector<double> h;
+  // (charge, channel count) classes per cut of the plain rule: the operator whose bond
+  // dimension is 2L^2 + 3L + 2 at the centre, the reference of the algorithmic flop count
+  std::vector<std::vector<std::pair<Charge, int>>> plain_cls;
   // Identifies the coefficients: a process-wide counter gives every new operator and every
   // set_one_body a fresh value, and copies keep it while their coefficients are equal.
   uint64_t version = next_mpo_version();
 };
 
-MpoHost build_mpo(int L, const double* h, const double* eri, double e0, bool two_body);
+// adjacent_window: at the cuts within this distance of the chain centre, pair channels next to
+// an operator site are named by the other side (see mpo.cpp); -1 gives the plain rule (left
+// pairs left of the centre, right pairs right of it) everywhere.
+MpoHost build_mpo(int L, const double* h, const double* eri, double e0, bool two_body, int adjacent_window = -1);
 // Kind of a channel (from MpoCut::key): 0 = identity so far, 1 = complete (H), 2 = one open
 // operator left of the cut (*so = spin orbital 2p + spin, *op = 0 creator / 1 annihilator),
 // 3 = anything else.

@@ -13,8 +13,11 @@
 // and the step's contribution sum_s 2 dt f(t_s) Im <kb_s|M|u_s>.  A_s^H = +i dt H(t_s) since
 // H is Hermitian, so the adjoint of an H application is an H application: the backward pass
 // runs the same fits, environments and H_eff products as the forward pass.  With MPS at
-// full bond dimension the result is the exact derivative of the discrete map; with
-// truncation it is the derivative of the map with the truncations held fixed.
+// full bond dimension the result is the exact derivative of the discrete map.  Below it every
+// adjoint stage (A_s^H applied to an MPS, and each sum of MPS) is a fit of its own, truncated
+// to Dmax like the forward stages: the result approximates the derivative of the truncated
+// map, with an error of the order of the truncation, and does not include the variation of
+// the kept singular subspaces with the amplitude.
 #include <cmath>
 
 #include "pulse.h"

@@ -54,7 +54,7 @@ _I32 = ct.POINTER(ct.c_int32)
 _I64 = ct.POINTER(ct.c_int64)
 _U8 = ct.POINTER(ct.c_uint8)
 
-NCOUNTERS = 20  # TDMPS_NCOUNTERS of include/tdmps.h
+NCOUNTERS = 21  # TDMPS_NCOUNTERS of include/tdmps.h
 TILE_CONFIGS = 10  # TDMPS_TILE_CONFIGS
 TILE_BUCKETS = 192  # TDMPS_TILE_BUCKETS
 
@@ -81,6 +81,10 @@ _SIGS = {
     "tdmps_mps_sectors": (ct.c_int32, [_P, _I32, _I32, _I64]),
     "tdmps_mps_get_blocks": (ct.c_int32, [_P, _D, _I64]),
     "tdmps_mps_to_dense": (ct.c_int32, [_P, _D, ct.c_int64]),
+    "tdmps_mps_from_dense": (ct.c_int32, [_P, ct.c_int32, ct.c_int32, ct.c_int32, _D, ct.c_int64, ct.c_int32,
+                                          ct.c_double, _PP]),
+    "tdmps_mps_save": (ct.c_int32, [_P, ct.c_char_p]),
+    "tdmps_mps_load": (ct.c_int32, [_P, ct.c_char_p, _PP]),
     "tdmps_mps_copy": (ct.c_int32, [_P, _PP]),
     "tdmps_mps_bond_dims": (ct.c_int32, [_P, _I32]),
     "tdmps_mps_destroy": (ct.c_int32, [_P]),
@@ -272,6 +276,27 @@ class MPS:
         out = ct.c_void_p()
         _check(_LIB.tdmps_mps_from_blocks(ctx.h, L, nsec.ctypes.data_as(_I32), sec.ctypes.data_as(_I32), _dp(d),
                                           d.size, ct.byref(out)))
+        return cls(out, L)
+
+    @classmethod
+    def from_dense(cls, ctx, vec, n_up, n_dn, Dmax=1 << 30, svd_cutoff=1e-12):
+        """Sequential-SVD state of a dense 4^L vector (zero outside the (n_up, n_dn) sector)."""
+        v = np.ascontiguousarray(np.asarray(vec, dtype=np.complex128)).view(np.float64)
+        L = int(round(np.log(v.size // 2) / np.log(4)))
+        out = ct.c_void_p()
+        _check(_LIB.tdmps_mps_from_dense(ctx.h, L, n_up + n_dn, n_up - n_dn, _dp(v), v.size, int(min(Dmax, 2 ** 31 - 1)),
+                                         float(svd_cutoff), ct.byref(out)))
+        return cls(out, L)
+
+    def save(self, path):
+        _check(_LIB.tdmps_mps_save(self.h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, ctx, path):
+        out = ct.c_void_p()
+        _check(_LIB.tdmps_mps_load(ctx.h, os.fsencode(path), ct.byref(out)))
+        with open(path, "rb") as f:  # chain length from the documented file header
+            L = int(np.frombuffer(f.read(12)[8:], dtype="<i4")[0])
         return cls(out, L)
 
     def sectors(self):

@@ -305,3 +305,40 @@ def random_state(L, Nu, Nd, D, sigma=1.0, seed=0):
         size = _panel_layout(left, right)[3]
         data.append(random_complex(rng, size) / np.sqrt(max(1, D)))
     return bonds, np.concatenate(data)
+
+
+def random_unitary(rng, n):
+    """Haar-like random unitary of order n (QR of a complex Gaussian, phases of R removed)."""
+    q, r = np.linalg.qr(random_complex(rng, (n, n)))
+    d = np.diagonal(r)
+    return q * (d / np.abs(d))[None, :]
+
+
+def rotate_bases(bonds, data, centre, seed):
+    """Rotates the bond bases of a determinant-basis state (det_basis_state) by a random
+    unitary per bond sector: bonds 1..centre and centre+2..L-1 (the bonds of the environments
+    of the two-site block at (centre, centre+1)).  Site tensor i becomes U_i^H A_i U_{i+1}
+    block by block, so the bond bases stay orthonormal, span the same determinants and become
+    complex.  Returns the new data (panel layout, same bonds)."""
+    rng = _rng(seed)
+    L = len(bonds) - 1
+    U = []
+    for i in range(L + 1):
+        rot = 1 <= i <= centre or centre + 2 <= i <= L - 1
+        U.append({(a, b): (random_unitary(rng, d) if rot else np.eye(d)) for a, b, d in bonds[i]})
+    out, off = [], 0
+    for i in range(L):
+        left = [((a, b), d) for a, b, d in bonds[i]]
+        right = [((a, b), d) for a, b, d in bonds[i + 1]]
+        offs, widths, blocks, size = _panel_layout(left, right)
+        A = np.array(data[off:off + size], dtype=np.complex128)
+        B = A.copy()
+        for (s, n), (t, col) in blocks.items():
+            ds, dt = left[s][1], right[t][1]
+            panel = A[offs[s]:offs[s] + ds * widths[s]].reshape(ds, widths[s])
+            blk = U[i][left[s][0]].conj().T @ panel[:, col:col + dt] @ U[i + 1][right[t][0]]
+            B[offs[s]:offs[s] + ds * widths[s]].reshape(ds, widths[s])[:, col:col + dt] = blk
+        out.append(B)
+        off += size
+    assert off == len(data)
+    return np.concatenate(out)

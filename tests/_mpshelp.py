@@ -40,3 +40,31 @@ def lib_to_oracle(m):
 def dense(m):
     """Dense vector of a library state through the oracle's own contraction."""
     return om.to_full(lib_to_oracle(m))
+
+
+def two_site_index(blocks, bonds, c):
+    """For the two-site tensor at bond (c, c+1) in the layout table of tdmps_heff_layout,
+    the dense index (a, s1 * 4 + s2, b) of every element, in layout order: returns
+    (flat layout offsets, flat dense indices into an array of shape (D_c, 16, D_{c+2}))."""
+    lo, ro = {}, {}
+    acc = 0
+    for nu, nd, d in bonds[c]:
+        lo[(nu, nd)] = acc
+        acc += d
+    Dl = acc
+    acc = 0
+    for nu, nd, d in bonds[c + 2]:
+        ro[(nu, nd)] = acc
+        acc += d
+    Dr = acc
+    offs, idx = [], []
+    for row in blocks:
+        nu, nd, n1, n2, Da, Db = [int(v) for v in row[:6]]
+        off = (int(row[6]) | (int(row[7]) << 31)) // 2
+        ld = int(row[8])
+        qb = (nu + (n1 & 1) + (n2 & 1), nd + (n1 >> 1) + (n2 >> 1))
+        a = lo[(nu, nd)] + np.arange(Da)
+        b = ro[qb] + np.arange(Db)
+        offs.append((off + np.arange(Da)[:, None] * ld + np.arange(Db)[None, :]).reshape(-1))
+        idx.append(((a[:, None] * 16 + (n1 * 4 + n2)) * Dr + b[None, :]).reshape(-1))
+    return np.concatenate(offs), np.concatenate(idx), (Dl, 16, Dr)

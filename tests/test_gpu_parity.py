@@ -168,12 +168,17 @@ def test_krylov_exact_and_norm_conserving(ctx, sys6):
     assert rel(dense(out), sys6.space.embed(propagate.exact(sys6.H, v, 0.05))) < 1e-7
 
 
-def test_heff_on_determinant_basis_matches_slater_condon(ctx):
+@pytest.mark.parametrize("window", [None, "-1"])
+def test_heff_on_determinant_basis_matches_slater_condon(ctx, window, monkeypatch):
     """With determinant bond bases, H_eff at the centre is the FCI matrix on the product
-    determinants; sampled outputs equal Slater-Condon sums over all inputs."""
+    determinants; sampled outputs equal Slater-Condon sums over all inputs.  With the default
+    routing of the operator's pair channels and with the plain rule, whose centre holds runs of
+    channels sharing one environment block (the share pass)."""
     L, D = 12, 128
     Nu, Nd = 6, 5
     h, eri, _ = synth.integrals(L)
+    if window is not None:
+        monkeypatch.setenv("TDMPS_MPO_ROUTING_WINDOW", window)
     mpo = T.MPO.from_integrals(ctx, h, eri, 0.0)
     bonds, data, S, Tset = synth.det_basis_state(L, Nu, Nd, D, seed=11)
     st = T.MPS.from_blocks(ctx, bonds, data)
@@ -186,7 +191,8 @@ def test_heff_on_determinant_basis_matches_slater_condon(ctx):
     tout = torch.zeros_like(tin)
     op.apply(tin.data_ptr(), tout.data_ptr())
     torch.cuda.synchronize()
-    assert ctx.counters()[8] > 0  # the plan holds shared-environment runs (share pass)
+    if window == "-1":
+        assert ctx.counters()[8] > 0  # the plan holds shared-environment runs (share pass)
     out = tout.cpu().numpy().view(np.complex128)
     masks, where = _theta_masks(L, c, blocks, S, Tset)
     sc = slater.SlaterCondon(h, eri)
@@ -255,7 +261,6 @@ def test_heff_full_size_sampled_outputs(ctx):
     ref = torch.empty_like(tin)
     cx.set_launch_mode(1)
     op.apply(tin.data_ptr(), ref.data_ptr())
-    assert cx.counters()[8] > 0  # shared-environment runs are part of this workload
     cx.autotune(T.FP64)
     cx.set_launch_mode(2)
     tout = torch.full_like(tin, float("nan"))
@@ -541,3 +546,61 @@ def test_compress_round_trip_long_columns(ctx):
     assert max(small.bond_dims()) <= 64
     f = abs(T.overlap(psi, small)) ** 2 / (n2 * T.overlap(small, small).real)
     assert np.isfinite(f) and 0 < f <= 1 + 1e-12
+
+
+@pytest.mark.parametrize("L,D", [(6, 1000), (6, 8), (8, 24), (10, 60)])
+def test_from_dense_matches_sequential_svd(ctx, L, D):
+    """tdmps_mps_from_dense against the oracle's sequential SVD (MPS section of Methods,
+    Eq. (mps)) on a random complex vector of the ionised sector: exact when D >= D_FCI,
+    else the same truncated state (default cut-off, every truncation gap above 1e-8)."""
+    occ = synth.ionized_determinant(L, L)
+    Q = synth.occ_charge(occ)
+    space = fci.Space.sector(L, *Q)
+    rng = np.random.default_rng(L + D)
+    v = space.embed(rng.standard_normal(space.dim) + 1j * rng.standard_normal(space.dim))
+    om.GAP_LOG.clear()
+    ref, disc = om.from_full(v, L, Q, Dmax=D)
+    st = T.MPS.from_dense(ctx, v, *Q, Dmax=D)
+    got, want = st.to_dense(), om.to_full(ref)
+    assert list(st.bond_dims()) == ref.bond_dims()
+    assert np.abs(got - want).max() < RTOL * np.abs(want).max()
+    if D >= max(om.dfci_bonds(L, Q)):
+        assert np.abs(got - v).max() < 1e-12 * np.abs(v).max()
+    else:
+        assert min(om.GAP_LOG) > 1e-8
+        assert abs(np.linalg.norm(v) ** 2 - np.linalg.norm(got) ** 2 - disc) < 1e-8 * np.linalg.norm(v) ** 2
+    bad = v.copy()
+    bad[0] = 1.0  # the vacuum lies outside the sector
+    with pytest.raises(T.TdmpsError) as e:
+        T.MPS.from_dense(ctx, bad, *Q)
+    assert e.value.code == -2
+
+
+def test_checkpoint_resume_is_bitwise(ctx, sys8, tmp_path):
+    """A Krylov run saved after one step and continued from the loaded file gives bitwise the
+    continuous run's states; the file round trip keeps sectors and bits; a corrupted or
+    truncated file is rejected."""
+    prm = T.fit_params(Dmax=48, n_sweeps=2)
+    psi = T.MPS.from_determinant(ctx, sys8.occ)
+    cont = []
+    for _ in range(3):
+        psi, _, _ = T.krylov_step(sys8.mpo, psi, 0.05, 5, True, prm)
+        cont.append(psi)
+    first, _, _ = T.krylov_step(sys8.mpo, T.MPS.from_determinant(ctx, sys8.occ), 0.05, 5, True, prm)
+    path = str(tmp_path / "psi1.tdmps")
+    first.save(path)
+    back = T.MPS.load(ctx, path)
+    assert back.L == 8 and back.sectors() == first.sectors()
+    assert np.array_equal(back.get_blocks().view(np.float64), cont[0].get_blocks().view(np.float64))
+    for k in (1, 2):
+        back, _, _ = T.krylov_step(sys8.mpo, back, 0.05, 5, True, prm)
+        assert np.array_equal(back.get_blocks().view(np.float64), cont[k].get_blocks().view(np.float64))
+    raw = bytearray(open(path, "rb").read())
+    raw[len(raw) // 2] ^= 0x10
+    bad = str(tmp_path / "bad.tdmps")
+    open(bad, "wb").write(bytes(raw))
+    with pytest.raises(T.TdmpsError):
+        T.MPS.load(ctx, bad)
+    open(bad, "wb").write(bytes(raw[: len(raw) // 3]))
+    with pytest.raises(T.TdmpsError):
+        T.MPS.load(ctx, bad)

@@ -27,23 +27,36 @@ def test_library_exports_every_declared_symbol(lib):
     assert sorted(T.symbols()) == declared
 
 
-@pytest.mark.parametrize("L", [2, 3, 4, 5])
-def test_mpo_equals_fci_on_fock_space(lib, L):
-    """The MPO contracted to a 4^L x 4^L matrix is the Hamiltonian of Eq. (hamil)."""
+@pytest.mark.parametrize("window", [None, "-1", "0", "1", "6"])
+@pytest.mark.parametrize("L", [2, 3, 4, 5, 6])
+def test_mpo_equals_fci_on_fock_space(lib, L, window, monkeypatch):
+    """The MPO contracted to a 4^L x 4^L matrix is the Hamiltonian of Eq. (hamil), for every
+    routing of the pair channels (plain rule, adjacent-operator rule at the centre cut, within
+    one cut of it, everywhere, and the default window)."""
+    if window is not None:
+        monkeypatch.setenv("TDMPS_MPO_ROUTING_WINDOW", window)
     h, eri, _ = synth.integrals(L, seed=40 + L)
     M = T.MPO.from_integrals(None, h, eri, 0.31)
     H = fci.hamiltonian(fci.Space.full(L), h, eri, 0.31).toarray()
     assert np.abs(M.to_dense() - H).max() < 1e-12
 
 
-def test_mpo_bond_dimension_formula(lib):
-    """Channel count at the chain centre: I, H, 4L single-operator channels, and the pair
-    channels of the left half: 2 + 4L + 2 C(L,2) + L^2 = 2L^2 + 3L + 2."""
-    for L in (6, 8, 12, 16):
+def test_mpo_bond_dimension_formula(lib, monkeypatch):
+    """Channel count at the chain centre under the plain rule: I, H, 4L single-operator
+    channels, and the pair channels of the left half: 2 + 4L + 2 C(L,2) + L^2 = 2L^2 + 3L + 2.
+    The default routing adds the pairs next to an operator site near the centre, and leaves
+    the chain ends alone."""
+    for L in (6, 8, 12, 16, 24):
         h, eri, _ = synth.integrals(L)
+        monkeypatch.setenv("TDMPS_MPO_ROUTING_WINDOW", "-1")
         d = T.MPO.from_integrals(None, h, eri).bond_dims()
         assert d[L // 2] == 2 * L * L + 3 * L + 2
         assert d[0] == 1 and d[L] == 1
+        monkeypatch.delenv("TDMPS_MPO_ROUTING_WINDOW")
+        r = T.MPO.from_integrals(None, h, eri).bond_dims()
+        assert r[L // 2] > d[L // 2]
+        w = L // 6
+        assert np.array_equal(r[: L // 2 - w], d[: L // 2 - w]) and np.array_equal(r[L // 2 + w + 1:], d[L // 2 + w + 1:])
 
 
 @pytest.mark.parametrize("L", [24, 30])
