@@ -293,6 +293,20 @@ tdmps_status tdmps_heff_layout(tdmps_heff op, int32_t which, int64_t* total_doub
                                int32_t* blocks);
 /* theta_out = H_eff theta_in; both device pointers (FP64 interleaved complex). */
 tdmps_status tdmps_heff_apply(tdmps_heff op, const void* theta_in_dev, void* theta_out_dev);
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): the same product as tdmps_heff_apply, bit for bit, with
+ * every buffer beyond theta_in / theta_out -- the H_eff intermediate, split-K partial sums,
+ * products of shared environment blocks and the task tables -- placed in a fixed device
+ * scratch of TDMPS_NOALLOC_SCRATCH_BYTES that the library holds on each GPU until the
+ * process ends (its address is resolved when a context is created on that GPU).  No device
+ * memory is allocated or freed (host-side planning uses the C++ heap).  Returns TDMPS_ERR_ARG,
+ * before any kernel runs and with theta_out untouched, when the operator needs more scratch
+ * than that (the intermediate alone is ~ MPO bond dimension x the two-site tensor: e.g. fine
+ * for L = 8 at D = 64, too large for L = 10 at D = 256).  Every call on a GPU reuses the same scratch
+ * and lays out its plan anew: calls that overlap in time on one GPU (other threads, other
+ * streams) race and must not be issued.  Returns after the context stream has finished. */
+#define TDMPS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+tdmps_status tdmps_heff_apply_noalloc(tdmps_heff op, const void* theta_in_dev, void* theta_out_dev);
 /* Contraction precision of later applies (TDMPS_FP64, TDMPS_FP32, TDMPS_BF16X3); the
  * environments are kept.  TDMPS_ERR_ARG for other values. */
 tdmps_status tdmps_heff_set_precision(tdmps_heff op, int32_t precision);

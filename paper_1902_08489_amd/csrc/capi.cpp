@@ -103,6 +103,7 @@ extern "C" tdmps_status tdmps_ctx_create(int32_t device, void* hip_stream, tdmps
     }
     c->phase_sync = std::getenv("TDMPS_PHASE_TIMING") != nullptr;
     dev_bind(device, c->stream);
+    noalloc_init(device);
     *out = c;
   });
 }
@@ -648,6 +649,28 @@ extern "C" tdmps_status tdmps_heff_apply(tdmps_heff h, const void* in, void* out
     } else {
       h->plan->launch(c, h->precision, c->batched != 0);
     }
+    dev_sync(c->stream);
+  });
+}
+
+extern "C" tdmps_status tdmps_heff_apply_noalloc(tdmps_heff h, const void* in, void* out) {
+  return guard([&] {
+    TDMPS_REQUIRE(h && in && out, TDMPS_ERR_ARG, "NULL argument");
+    TDMPS_REQUIRE(in != out, TDMPS_ERR_ARG, "in-place apply is not supported");
+    Ctx* c = h->ctx;
+    dev_set_device(c->device);
+    size_t cap = 0;
+    char* base = (char*)noalloc_scratch(c->device, &cap);
+    TDMPS_REQUIRE(base != nullptr, TDMPS_ERR_HIP, "no-allocation scratch not resolved on this device");
+    // the plan (intermediate, split-K parts, shared products, task tables) is laid out in the
+    // scratch from its start on every call: another call on this GPU may have reused it
+    Arena arena{base, cap, 0};
+    Contractor C;
+    C.ctx = c;
+    C.precision = h->precision;
+    auto plan = heff_plan(C, *h->lops, *h->rops, (const cplx*)in, h->kl, h->ket_l, h->ket_r, (cplx*)out, h->bl,
+                          h->bra_l, h->bra_r, cplx{1, 0}, false, &arena);
+    plan->launch(c, h->precision, true);
     dev_sync(c->stream);
   });
 }

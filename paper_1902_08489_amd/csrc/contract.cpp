@@ -630,7 +630,7 @@ void heff_apply(Contractor& C, const SideOps& lops, const SideOps& rops, const c
 std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const SideOps& rops, const cplx* theta_in,
                                     const TwoLayout& kl, const Bond& ket_l, const Bond& ket_r, cplx* theta_out,
                                     const TwoLayout& bl, const Bond& bra_l, const Bond& bra_r, cplx alpha,
-                                    bool accumulate) {
+                                    bool accumulate, Arena* arena) {
   TDMPS_REQUIRE(lops.cut == rops.cut, TDMPS_ERR_ARG, "internal: middle cuts differ");
   auto plan = std::make_unique<HeffPlan>();
   plan->out = theta_out;
@@ -840,14 +840,14 @@ std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const Si
       }
     }
   }
-  plan->T = DevBuf(tsize * sizeof(cplx));
+  plan->T = arena ? arena->view(tsize * sizeof(cplx)) : DevBuf(tsize * sizeof(cplx));
   cplx* Tb = plan->T.c();
   for (size_t ri = 0; ri < rows.size(); ++ri)
     if (row_task[ri] != (size_t)-1) p1.tasks[row_task[ri]].C = Tb + rows[ri].off;
   if (!shared_rows.empty()) {
     // the shared products get a buffer of their own: keeping T at the size of its rows keeps
     // the caching allocator's reuse of the large T buffers from bond to bond
-    plan->X = DevBuf(xsize * sizeof(cplx));
+    plan->X = arena ? arena->view(xsize * sizeof(cplx)) : DevBuf(xsize * sizeof(cplx));
     cplx* Xb = plan->X.c();
     for (const auto& sr : shared_rows) {
       const Row& R = rows[sr.row];
@@ -919,6 +919,7 @@ std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const Si
         }
     plan->alg_flops = alg;
   }
+  p1.arena = p1b.arena = p2.arena = arena;
   p1.finalize(C.ctx, C.precision);
   p1b.finalize(C.ctx, C.precision);
   p2.finalize(C.ctx, C.precision);

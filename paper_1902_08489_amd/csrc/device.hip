@@ -186,6 +186,12 @@ void dev_h2d(void* dst, const void* src, size_t bytes, void* stream) {
   use->stamp = ++g_pin_clock;
 }
 
+void dev_h2d_wait(void* dst, const void* src, size_t bytes, void* stream) {
+  if (!bytes) return;
+  check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, (hipStream_t)stream), "hipMemcpyAsync H2D");
+  check(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+}
+
 // Readbacks land in a pinned bounce buffer per (device, stream): a copy into pageable memory
 // is staged by the runtime and costs far more latency than the copy itself, and the host
 // waits for every readback (singular values, convergence counters, scalar results).

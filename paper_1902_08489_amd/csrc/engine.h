@@ -40,12 +40,13 @@ tdmps_status guard(F&& f) {
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool own = true;  // false: a view of memory owned elsewhere (an Arena), never freed
   DevBuf() = default;
   explicit DevBuf(size_t b);
   ~DevBuf();
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), own(o.own) {
     o.p = nullptr;
     o.bytes = 0;
   }
@@ -54,6 +55,7 @@ struct DevBuf {
       release();
       p = o.p;
       bytes = o.bytes;
+      own = o.own;
       o.p = nullptr;
       o.bytes = 0;
     }
@@ -61,6 +63,15 @@ struct DevBuf {
   }
   void release();
   cplx* c() const { return (cplx*)p; }
+};
+
+// Bump allocation over a fixed device region (the no-allocation entry point's scratch):
+// take() hands out 256-byte aligned pieces and throws TDMPS_ERR_ARG beyond the capacity.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  void* take(size_t bytes);
+  DevBuf view(size_t bytes);  // non-owning DevBuf over take(bytes)
 };
 
 // ---------------------------------------------------------------- bonds and layouts
@@ -247,6 +258,9 @@ struct GemmPlan {
   size_t ntasks_built = 0, nsegs_built = 0;
   size_t task_count() const { return final_ ? ntasks_built : tasks.size(); }
   size_t seg_count() const { return final_ ? nsegs_built : segs.size(); }
+  // with an arena, the split-K workspace and the tables are placed in it and the upload waits
+  // for its completion (nothing is allocated)
+  Arena* arena = nullptr;
   void finalize(Ctx* ctx, int precision);
   // batched: one grouped launch per tile shape (default); else one launch per task (the
   // per-block baseline the grouped launch is compared with)
@@ -327,10 +341,11 @@ struct HeffPlan {
   double alg_flops = 0;
   void launch(Ctx* ctx, int precision, bool batched = true);
 };
+// arena (nullable): intermediates, workspaces and task tables in that region, no allocation
 std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const SideOps& rops, const cplx* theta_in,
                                     const TwoLayout& kl, const Bond& ket_l, const Bond& ket_r, cplx* theta_out,
                                     const TwoLayout& bl, const Bond& bra_l, const Bond& bra_r, cplx alpha,
-                                    bool accumulate);
+                                    bool accumulate, Arena* arena = nullptr);
 void heff_apply(Contractor& C, const SideOps& lops, const SideOps& rops, const cplx* theta_in, const TwoLayout& kl,
                 const Bond& ket_l, const Bond& ket_r, cplx* theta_out, const TwoLayout& bl, const Bond& bra_l,
                 const Bond& bra_r, cplx alpha, bool accumulate, double* alg_flops);

@@ -105,6 +105,9 @@ void* dev_alloc(size_t bytes);  // returns nullptr when out of memory
 void dev_free(void* p);
 void dev_alloc_stats(double* count, double* seconds);  // hipMalloc calls and seconds so far (process)
 void dev_h2d(void* dst, const void* src, size_t bytes, void* stream);
+// H2D copy on the stream straight from host memory (no staging block), returning after the
+// stream has completed it
+void dev_h2d_wait(void* dst, const void* src, size_t bytes, void* stream);
 void dev_d2h(void* dst, const void* src, size_t bytes, void* stream);  // host data valid on return
 void dev_d2d(void* dst, const void* src, size_t bytes, void* stream);
 void dev_zero(void* dst, size_t bytes, void* stream);  // fill kernel (no memset nodes)
@@ -122,6 +125,12 @@ void* graph_end(void* stream);    // instantiated graph
 void graph_abort(void* stream);   // ends a failed capture and drops it
 void graph_launch(void* exec, void* stream);
 void graph_destroy(void* exec);
+
+// Scratch of the no-allocation entry point (noalloc.hip): noalloc_init resolves the address of
+// the device's copy (call with that device current); noalloc_scratch returns it (nullptr before
+// noalloc_init) and its capacity.
+void noalloc_init(int device);
+void* noalloc_scratch(int device, size_t* cap);
 
 // launchers (all asynchronous on `stream`)
 // Runs tiles tile_offset .. tile_offset + total_tiles - 1 of the tile table.

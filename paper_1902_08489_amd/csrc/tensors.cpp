@@ -21,9 +21,28 @@ DevBuf::DevBuf(size_t b) : bytes(b) {
 }
 DevBuf::~DevBuf() { release(); }
 void DevBuf::release() {
-  if (p) dev_free(p);
+  if (p && own) dev_free(p);
   p = nullptr;
   bytes = 0;
+  own = true;
+}
+
+void* Arena::take(size_t b) {
+  const size_t start = (used + 255) & ~(size_t)255;
+  TDMPS_REQUIRE(start <= cap && b <= cap - start, TDMPS_ERR_ARG,
+                "the operation needs more than the " + std::to_string(cap >> 20) +
+                    " MiB of the no-allocation scratch (intermediates and task tables)");
+  used = start + b;
+  return base + start;
+}
+
+DevBuf Arena::view(size_t b) {
+  DevBuf d;
+  if (b == 0) return d;
+  d.p = take(b);
+  d.bytes = b;
+  d.own = false;
+  return d;
 }
 
 // ---------------------------------------------------------------- bonds and layouts
@@ -268,7 +287,7 @@ void GemmPlan::finalize(Ctx* ctx, int precision) {
   }
   if (out.empty()) return;
   if (ws > 0) {
-    wspace = DevBuf(ws * sizeof(cplx));
+    wspace = arena ? arena->view(ws * sizeof(cplx)) : DevBuf(ws * sizeof(cplx));
     for (auto& po : part_of) out[po.first].C = wspace.c() + po.second;
     for (size_t k = 0; k < red.size(); ++k) red[k].parts = wspace.c() + red_base[k];
     nred_tasks = (int)red.size();
@@ -357,8 +376,14 @@ void GemmPlan::finalize(Ctx* ctx, int precision) {
     if (!tmap[cfg].empty()) std::memcpy(img.data() + o_tile[cfg], tmap[cfg].data(), tmap[cfg].size() * sizeof(int32_t));
   }
   if (!extra.empty()) std::memcpy(img.data() + o_extra, extra.data(), extra.size());
-  dtab = DevBuf(bytes);
-  dev_h2d(dtab.p, img.data(), bytes, ctx->stream);
+  if (arena) {
+    // the image goes back to a reuse pool on return: copy from it and wait
+    dtab = arena->view(bytes);
+    dev_h2d_wait(dtab.p, img.data(), bytes, ctx->stream);
+  } else {
+    dtab = DevBuf(bytes);
+    dev_h2d(dtab.p, img.data(), bytes, ctx->stream);
+  }
   char* b = (char*)dtab.p;
   dextra = extra.empty() ? nullptr : b + o_extra;
   dsegs = (const GemmSeg*)(b + o_segs);

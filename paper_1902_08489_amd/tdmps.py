@@ -104,6 +104,7 @@ _SIGS = {
     "tdmps_heff_create": (ct.c_int32, [_P, _P, _P, ct.c_int32, ct.c_int32, _PP]),
     "tdmps_heff_layout": (ct.c_int32, [_P, ct.c_int32, _I64, _I64, _I32]),
     "tdmps_heff_apply": (ct.c_int32, [_P, _P, _P]),
+    "tdmps_heff_apply_noalloc": (ct.c_int32, [_P, _P, _P]),
     "tdmps_heff_set_precision": (ct.c_int32, [_P, ct.c_int32]),
     "tdmps_heff_flops": (ct.c_int32, [_P, _D]),
     "tdmps_heff_destroy": (ct.c_int32, [_P]),
@@ -464,6 +465,10 @@ class Heff:
 
     def apply(self, in_ptr, out_ptr):
         _check(_LIB.tdmps_heff_apply(self.h, ct.c_void_p(in_ptr), ct.c_void_p(out_ptr)))
+
+    def apply_noalloc(self, in_ptr, out_ptr):
+        """The same product in the library's fixed device scratch (no allocation)."""
+        _check(_LIB.tdmps_heff_apply_noalloc(self.h, ct.c_void_p(in_ptr), ct.c_void_p(out_ptr)))
 
     def set_precision(self, precision):
         _check(_LIB.tdmps_heff_set_precision(self.h, int(precision)))
