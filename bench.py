@@ -126,6 +126,10 @@ def main():
                     choices=["heff", "krylov", "precision", "gradient", "rdm", "green"])
     ap.add_argument("--dt", type=float, default=None)
     ap.add_argument("--sweeps", type=int, default=1, help="fit sweeps per H application (Krylov workloads)")
+    ap.add_argument("--conv-tol", type=float, default=0.0, help="fit convergence tolerance on |C|^2 (0: all sweeps)")
+    ap.add_argument("--init", default="random", choices=["random", "det"],
+                    help="Krylov workloads: random block state at full D, or the ionised determinant")
+    ap.add_argument("--observe", type=int, default=0, help="Krylov workloads: record norm, energy, dipole every step")
     ap.add_argument("--rk4-steps", type=int, default=200)
     ap.add_argument("--checkpoint", type=int, default=20)
     ap.add_argument("--fd", type=int, default=0, help="gradient workload: also central finite differences")
@@ -419,9 +423,14 @@ def other_workload(args, progress):
         mu_pq = synth.dipole_matrix(L, ell)
         H = T.MPO.from_integrals(ctx, h, eri, 0.0)
         MU = T.MPO.one_body(ctx, mu_pq)
-        bk, dk = synth.random_state(L, Nu, Nd, D, sigma=1.0, seed=L + 5)
-        psi0 = T.MPS.from_blocks(ctx, bk, dk)
-        psi0.scale(1.0 / np.sqrt(T.overlap(psi0, psi0).real))
+        if args.init == "det":
+            psi0 = T.MPS.from_determinant(ctx, synth.ionized_determinant(L, N0))
+            init = "the ionised determinant"
+        else:
+            bk, dk = synth.random_state(L, Nu, Nd, D, sigma=1.0, seed=L + 5)
+            psi0 = T.MPS.from_blocks(ctx, bk, dk)
+            psi0.scale(1.0 / np.sqrt(T.overlap(psi0, psi0).real))
+            init = "a random block state at full D"
         progress(f"L={L} D={D} state built")
 
         def observables(psi):
@@ -429,41 +438,63 @@ def other_workload(args, progress):
             return {"norm2": n2, "energy": T.expect(H, psi, psi).real / n2, "dipole": T.expect(MU, psi, psi).real / n2}
 
         def run(prec, nsteps, warm):
-            prm = T.fit_params(Dmax=D, n_sweeps=args.sweeps, precision=PREC[prec])
+            prm = T.fit_params(Dmax=D, n_sweeps=args.sweeps, conv_tol=args.conv_tol, precision=PREC[prec])
             psi = psi0
             for _ in range(warm):
                 psi, _, _ = T.krylov_step(H, psi, dt, m, True, prm)
+            traj = []
             torch.cuda.synchronize()
             t0 = time.perf_counter()
+            t_obs = 0.0
             for k in range(nsteps):
                 psi, _, _ = T.krylov_step(H, psi, dt, m, True, prm)
+                if args.observe:
+                    # observables are outside the step time (their sweeps are not part of a step)
+                    torch.cuda.synchronize()
+                    to = time.perf_counter()
+                    traj.append({"t": (warm + k + 1) * dt, **observables(psi), "bond_max": int(max(psi.bond_dims()))})
+                    t_obs += time.perf_counter() - to
                 progress(f"{prec} Krylov step {k + 1} of {nsteps}: {time.perf_counter() - t0:.1f} s")
             torch.cuda.synchronize()
-            return (time.perf_counter() - t0) / nsteps, observables(psi)
+            return (time.perf_counter() - t0 - t_obs) / nsteps, observables(psi), traj
 
         os.environ["TDMPS_PROGRESS"] = "1"
+        sweeps_txt = f"{args.sweeps} sweep(s) per fit" + (f" (stop at |C|^2 change < {args.conv_tol})"
+                                                           if args.conv_tol > 0 else "")
         if args.workload == "krylov":
-            sps, obs = run(args.precision, args.steps, args.warmup)
+            sps, obs, traj = run(args.precision, args.steps, args.warmup)
             line.update({"metric": f"Krylov steps/s @L={L} D={D} m={m}", "value": 1.0 / sps, "unit": "steps/s",
                          "ms_per_step": sps * 1e3, "dtype": args.precision,
                          "config": {"workload": f"Krylov time step, L={L} N={N0 - 1} D={D} m={m} dt={dt}, "
-                                                f"{args.sweeps} sweep(s) per fit, from a random block state at full D",
+                                                f"{sweeps_txt}, from {init}",
                                     "precision": args.precision},
                          "observables_after": obs})
+            if traj:
+                line["trajectory"] = traj
+                e = [x["energy"] for x in traj]
+                line["energy_drift"] = max(e) - min(e)
         else:
             res = {}
+            trajs = {}
             for prec in ("fp64", "fp32", "bf16x3"):
-                sps, obs = run(prec, args.steps, 0)
+                sps, obs, traj = run(prec, args.steps, 0)
                 res[prec] = {"s_per_step": sps, **obs}
+                trajs[prec] = traj
             ref = res["fp64"]
             for prec in ("fp32", "bf16x3"):
                 res[prec]["rel_err_vs_fp64"] = {k: abs(res[prec][k] - ref[k]) / abs(ref[k])
                                                 for k in ("norm2", "energy", "dipole")}
+                if trajs[prec]:
+                    res[prec]["rel_err_vs_fp64_per_step"] = [
+                        {k: abs(a[k] - b[k]) / abs(b[k]) for k in ("norm2", "energy", "dipole")}
+                        for a, b in zip(trajs[prec], trajs["fp64"])]
+                    res[prec]["max_rel_err_vs_fp64_over_steps"] = {
+                        k: max(x[k] for x in res[prec]["rel_err_vs_fp64_per_step"]) for k in ("norm2", "energy", "dipole")}
             best = min(("fp32", "bf16x3"), key=lambda p: res[p]["s_per_step"])
             line.update({"metric": f"Krylov steps/s @L={L} D={D}, mixed vs FP64", "value": 1.0 / res[best]["s_per_step"],
                          "unit": "steps/s", "ms_per_step": res[best]["s_per_step"] * 1e3, "dtype": best,
                          "config": {"workload": f"Krylov time step, L={L} N={N0 - 1} D={D} m={m} dt={dt}, "
-                                                f"{args.sweeps} sweep(s) per fit, from a random block state at full D"},
+                                                f"{sweeps_txt}, from {init}; {args.steps} steps per precision"},
                          "speedup_vs_fp64": ref["s_per_step"] / res[best]["s_per_step"], "per_precision": res})
     else:
         L = args.L or 16
