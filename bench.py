@@ -130,6 +130,10 @@ def main():
     ap.add_argument("--init", default="random", choices=["random", "det"],
                     help="Krylov workloads: random block state at full D, or the ionised determinant")
     ap.add_argument("--observe", type=int, default=0, help="Krylov workloads: record norm, energy, dipole every step")
+    ap.add_argument("--precisions", default="fp64,fp32,bf16x3",
+                    help="precision workload: the precisions to run (FP64 is the reference)")
+    ap.add_argument("--reference", default=None,
+                    help="precision workload without fp64: JSON line of an FP64 run of the same workload")
     ap.add_argument("--rk4-steps", type=int, default=200)
     ap.add_argument("--checkpoint", type=int, default=20)
     ap.add_argument("--fd", type=int, default=0, help="gradient workload: also central finite differences")
@@ -476,12 +480,26 @@ def other_workload(args, progress):
         else:
             res = {}
             trajs = {}
-            for prec in ("fp64", "fp32", "bf16x3"):
+            precs = [p for p in args.precisions.split(",") if p]
+            if not precs or any(p not in PREC for p in precs):
+                raise SystemExit("--precisions: a comma-separated list of fp64, fp32, bf16x3")
+            ref_src = "this run"
+            if "fp64" not in precs:
+                # FP64 reference trajectory of an earlier run of the same workload
+                if not args.reference:
+                    raise SystemExit("--precisions without fp64 needs --reference (an FP64 line of this workload)")
+                with open(args.reference) as f:
+                    ref_line = json.loads(f.read().strip().splitlines()[-1])
+                res["fp64"] = ref_line["per_precision"]["fp64"]
+                trajs["fp64"] = res["fp64"].get("trajectory", [])
+                ref_src = f"the FP64 run in {os.path.basename(args.reference)}"
+            for prec in precs:
                 sps, obs, traj = run(prec, args.steps, 0)
-                res[prec] = {"s_per_step": sps, **obs}
+                res[prec] = {"s_per_step": sps, **obs, "trajectory": traj}
                 trajs[prec] = traj
             ref = res["fp64"]
-            for prec in ("fp32", "bf16x3"):
+            low = [p for p in precs if p != "fp64"]
+            for prec in low:
                 res[prec]["rel_err_vs_fp64"] = {k: abs(res[prec][k] - ref[k]) / abs(ref[k])
                                                 for k in ("norm2", "energy", "dipole")}
                 if trajs[prec]:
@@ -490,11 +508,12 @@ def other_workload(args, progress):
                         for a, b in zip(trajs[prec], trajs["fp64"])]
                     res[prec]["max_rel_err_vs_fp64_over_steps"] = {
                         k: max(x[k] for x in res[prec]["rel_err_vs_fp64_per_step"]) for k in ("norm2", "energy", "dipole")}
-            best = min(("fp32", "bf16x3"), key=lambda p: res[p]["s_per_step"])
+            best = min(low, key=lambda p: res[p]["s_per_step"]) if low else "fp64"
             line.update({"metric": f"Krylov steps/s @L={L} D={D}, mixed vs FP64", "value": 1.0 / res[best]["s_per_step"],
                          "unit": "steps/s", "ms_per_step": res[best]["s_per_step"] * 1e3, "dtype": best,
                          "config": {"workload": f"Krylov time step, L={L} N={N0 - 1} D={D} m={m} dt={dt}, "
-                                                f"{sweeps_txt}, from {init}; {args.steps} steps per precision"},
+                                                f"{sweeps_txt}, from {init}; {args.steps} steps per precision",
+                                    "precisions_run": precs, "fp64_reference": ref_src},
                          "speedup_vs_fp64": ref["s_per_step"] / res[best]["s_per_step"], "per_precision": res})
     else:
         L = args.L or 16
