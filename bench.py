@@ -236,7 +236,9 @@ def main():
                             "roofline_frac": flops / (float(np.mean(pk)) * 1e-3) / 1e12 / PEAK[pname],
                             "max_abs_err_rel_to_max_fp64": float(np.abs(low - out).max() / np.abs(out).max()),
                             "rel_l2_err_vs_fp64": float(np.linalg.norm(low - out) / np.linalg.norm(out)),
-                            "speedup_vs_fp64": ms_step / pms}
+                            "speedup_vs_fp64": ms_step / pms,
+                            "operand_storage": "fp64" if os.environ.get("TDMPS_MIXED_STORAGE") == "0" else "fp32",
+                            "T_bytes": ctx.counters()[3]}
             progress(f"{pname}: {pms:.2f} ms per apply")
         op.set_precision(PREC[args.precision])
     # batching baseline: the same H_eff*theta with one kernel launch per block product

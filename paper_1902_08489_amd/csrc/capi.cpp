@@ -31,6 +31,15 @@ struct tdmps_heff_s {
 
 namespace {
 
+// Parameters of the library's own contractions (no caller parameters): FP64 unless stated,
+// grouped launches.  A zero-initialised tdmps_fit_params would select the per-block baseline.
+tdmps_fit_params internal_params(int32_t precision = TDMPS_FP64) {
+  tdmps_fit_params p{};
+  p.precision = precision;
+  p.batched = 1;
+  return p;
+}
+
 Contractor make_contractor(Ctx* ctx, const tdmps_fit_params* prm) {
   dev_bind(ctx->device, ctx->stream);
   Contractor C;
@@ -102,6 +111,7 @@ extern "C" tdmps_status tdmps_ctx_create(int32_t device, void* hip_stream, tdmps
       c->own_stream = true;
     }
     c->phase_sync = std::getenv("TDMPS_PHASE_TIMING") != nullptr;
+    if (const char* ms = std::getenv("TDMPS_MIXED_STORAGE")) c->mixed_storage = std::atoi(ms) != 0;
     dev_bind(device, c->stream);
     noalloc_init(device);
     *out = c;
@@ -347,7 +357,7 @@ extern "C" tdmps_status tdmps_mps_from_dense(tdmps_ctx ctx, int32_t L, int32_t N
     TDMPS_REQUIRE(((N + twoSz) & 1) == 0 && N >= 0 && std::abs(twoSz) <= N, TDMPS_ERR_SECTOR,
                   "N and 2Sz must have equal parity with |2Sz| <= N");
     TDMPS_REQUIRE(svd_cutoff >= 0 && std::isfinite(svd_cutoff), TDMPS_ERR_ARG, "bad svd_cutoff");
-    tdmps_fit_params prm{};
+    tdmps_fit_params prm = internal_params();
     Contractor C = make_contractor(ctx, &prm);
     *out = mps_from_dense(C, L, Charge((N + twoSz) / 2, (N - twoSz) / 2), coeffs, Dmax, svd_cutoff);
   });
@@ -474,8 +484,7 @@ extern "C" tdmps_status tdmps_krylov_ground(tdmps_mpo H, tdmps_mps psi, int32_t 
 extern "C" tdmps_status tdmps_mps_one_rdm(tdmps_mps psi, double* gamma) {
   return guard([&] {
     TDMPS_REQUIRE(psi && gamma, TDMPS_ERR_ARG, "NULL argument");
-    tdmps_fit_params prm{};
-    prm.precision = TDMPS_FP64;
+    tdmps_fit_params prm = internal_params();
     Contractor C = make_contractor(psi->ctx, &prm);
     const std::vector<std::complex<double>> g = one_rdm(C, psi);
     publish(psi->ctx, C);
@@ -536,8 +545,7 @@ extern "C" tdmps_status tdmps_heff_create(tdmps_mpo H, tdmps_mps bra, tdmps_mps 
     h->ctx = bra->ctx;
     h->precision = precision;
     h->H = &H->host;
-    tdmps_fit_params prm{};
-    prm.precision = precision;
+    tdmps_fit_params prm = internal_params(precision);
     Contractor C = make_contractor(bra->ctx, &prm);
     const MpoHost& W = H->host;
     auto E = std::make_unique<Env>(env_left_boundary(C.ctx, bra->bond[0], ket->bond[0]));
@@ -612,8 +620,7 @@ extern "C" tdmps_status tdmps_heff_apply(tdmps_heff h, const void* in, void* out
       graph_destroy(h->graph);
       h->graph = nullptr;
       h->plan.reset();
-      tdmps_fit_params prm{};
-      prm.precision = h->precision;
+      tdmps_fit_params prm = internal_params(h->precision);
       Contractor C = make_contractor(c, &prm);
       h->plan = heff_plan(C, *h->lops, *h->rops, (const cplx*)in, h->kl, h->ket_l, h->ket_r, (cplx*)out, h->bl,
                           h->bra_l, h->bra_r, cplx{1, 0}, false);
@@ -696,8 +703,7 @@ extern "C" tdmps_status tdmps_heff_flops(tdmps_heff h, double* flops) {
     if (!h->plan) {
       // plan once on scratch pointers to count
       DevBuf a(std::max<int64_t>(h->kl.size, 1) * sizeof(cplx)), b(std::max<int64_t>(h->bl.size, 1) * sizeof(cplx));
-      tdmps_fit_params prm{};
-      prm.precision = h->precision;
+      tdmps_fit_params prm = internal_params(h->precision);
       Contractor C = make_contractor(h->ctx, &prm);
       auto p = heff_plan(C, *h->lops, *h->rops, a.c(), h->kl, h->ket_l, h->ket_r, b.c(), h->bl, h->bra_l, h->bra_r,
                          cplx{1, 0}, false);

@@ -603,6 +603,7 @@ Env env_right_update(Contractor& C, const SideOps& ops, const cplx* bra_site, co
 
 void HeffPlan::launch(Ctx* ctx, int precision, bool batched) {
   if (!accumulate && out_size) dev_zero(out, out_size * sizeof(cplx), ctx->stream);
+  if (ops32) launch_to_f32(theta_in, theta32.p, theta_size, ctx->stream);
   p1.launch(ctx, precision, batched);
   p1b.launch(ctx, precision, batched);
   if (!share_host.empty()) {
@@ -637,6 +638,38 @@ std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const Si
   plan->out_size = bl.size;
   plan->accumulate = accumulate;
   const int nmid = (int)lops.ch.size();
+  // Mixed precisions: operands and the T intermediate in FP32 storage.  Every environment
+  // operator buffer referenced by the two sides gets an FP32 copy now; theta_in is converted by
+  // every launch (its contents change between launches).  Pointers into an FP32 copy keep the
+  // element offsets of the FP64 buffer.
+  const bool s32 = C.precision != TDMPS_FP64 && C.ctx->mixed_storage;
+  plan->ops32 = s32;
+  std::vector<std::pair<const Blocks*, const void*>> shadow_of;
+  auto f32_at = [](const void* base, int64_t off) { return (const cplx*)((const char*)base + off * 8); };
+  auto to32 = [&](const Blocks* src, const cplx* p) -> const cplx* {
+    for (const auto& so : shadow_of)
+      if (so.first == src) return f32_at(so.second, p - src->data.c());
+    throw Error(TDMPS_ERR_NUMERIC, "internal: operand buffer without an FP32 copy");
+  };
+  if (s32) {
+    auto add = [&](const SideOps& o) {
+      for (const auto& ch : o.ch)
+        for (const auto& ref : ch.ref) {
+          bool seen = false;
+          for (const auto& so : shadow_of) seen |= so.first == ref.src;
+          if (seen || ref.src->size == 0) continue;
+          plan->shadows.push_back(arena ? arena->view(ref.src->size * 8) : DevBuf(ref.src->size * 8));
+          launch_to_f32(ref.src->data.c(), plan->shadows.back().p, ref.src->size, C.ctx->stream);
+          shadow_of.push_back({ref.src, plan->shadows.back().p});
+        }
+    };
+    add(lops);
+    add(rops);
+    plan->theta_in = theta_in;
+    plan->theta_size = kl.size;
+    plan->theta32 = arena ? arena->view(std::max<int64_t>(kl.size, 1) * 8) : DevBuf(std::max<int64_t>(kl.size, 1) * 8);
+  }
+  const int64_t esz = s32 ? 8 : (int64_t)sizeof(cplx);  // bytes per element of T
   // Runs over the middle cut: identical structure on the right; on the left every pattern
   // either stacked over the run or shared by all of its channels (shared[r][k]).  Shared
   // patterns are computed per channel in a stage of their own (p1b below), the rest as one
@@ -783,7 +816,12 @@ std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const Si
       }
       Dsk = ket_l.dim[sk];
       A = ref.src->stack(ref.grp, sk) + (int64_t)ref.idx * Ds * Dsk;
-      B = theta_in + kl.panel_off[sk] + kl.col[sk][s1p * 4 + first];
+      const int64_t boff = kl.panel_off[sk] + kl.col[sk][s1p * 4 + first];
+      B = theta_in + boff;
+      if (s32) {
+        A = to32(ref.src, A);
+        B = f32_at(plan->theta32.p, boff);
+      }
       return sk;
     };
     // stacked patterns: one product over all channels of the run
@@ -796,6 +834,7 @@ std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const Si
       if (!main_task) {
         row_task[ri] = p1.tasks.size();
         p1.begin_task(nullptr, 0, R.width, run.n * Ds, R.width, 1, false);
+        if (s32) p1.tasks.back().flags |= GEMM_OUT32;
         main_task = true;
       }
       p1.add_seg(A, 0, 0, Dsk, OP_N, B, 0, 0, kl.width[sk], OP_N, Dsk, 1, cplx{lo.ref[k].coef, 0.0});
@@ -833,6 +872,7 @@ std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const Si
         st.nrun = run.n;
         st.nq = nq;
         st.accum = main_task ? 1 : 0;
+        st.out32 = s32 ? 1 : 0;
         sr.share = plan->share_host.size();
         plan->share_host.push_back(st);
         plan->share_max_blk = std::max(plan->share_max_blk, blk);
@@ -840,10 +880,11 @@ std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const Si
       }
     }
   }
-  plan->T = arena ? arena->view(tsize * sizeof(cplx)) : DevBuf(tsize * sizeof(cplx));
-  cplx* Tb = plan->T.c();
+  plan->T = arena ? arena->view(tsize * esz) : DevBuf(tsize * esz);
+  // element off of T (FP64 or FP32 complex)
+  auto t_at = [&](int64_t off) { return (cplx*)((char*)plan->T.p + off * esz); };
   for (size_t ri = 0; ri < rows.size(); ++ri)
-    if (row_task[ri] != (size_t)-1) p1.tasks[row_task[ri]].C = Tb + rows[ri].off;
+    if (row_task[ri] != (size_t)-1) p1.tasks[row_task[ri]].C = t_at(rows[ri].off);
   if (!shared_rows.empty()) {
     // the shared products get a buffer of their own: keeping T at the size of its rows keeps
     // the caching allocator's reuse of the large T buffers from bond to bond
@@ -854,7 +895,7 @@ std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const Si
       const int64_t blk = (int64_t)bra_l.dim[R.s] * R.width;
       for (size_t q = 0; q < sr.xtask.size(); ++q) p1b.tasks[sr.xtask[q]].C = Xb + sr.xoff + (int64_t)q * blk;
       ShareTask& st = plan->share_host[sr.share];
-      st.T = Tb + R.off;
+      st.T = t_at(R.off);
       st.X = Xb + sr.xoff;
     }
     // the share tasks and their coefficients travel with p1b's task tables
@@ -881,8 +922,9 @@ std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const Si
         started = true;
       }
       const OpRef& ref = *fs.ref;
-      const cplx* A = Tb + R.off + R.coff[fs.s2p];
+      const cplx* A = t_at(R.off + R.coff[fs.s2p]);
       const cplx* B = ref.src->stack(ref.grp, tk) + (int64_t)ref.idx * Dt * Dtk;
+      if (s32) B = to32(ref.src, B);
       p2.add_seg(A, 0, (int64_t)Ds * R.width, R.width, OP_N, B, 0, (int64_t)Dt * Dtk, Dtk, OP_T, Dtk, run.n,
                  cmul(cplx{ref.coef, 0.0}, alpha));
     }
@@ -920,6 +962,7 @@ std::unique_ptr<HeffPlan> heff_plan(Contractor& C, const SideOps& lops, const Si
     plan->alg_flops = alg;
   }
   p1.arena = p1b.arena = p2.arena = arena;
+  p1.ops32 = p1b.ops32 = p2.ops32 = s32;
   p1.finalize(C.ctx, C.precision);
   p1b.finalize(C.ctx, C.precision);
   p2.finalize(C.ctx, C.precision);

@@ -74,6 +74,16 @@ __global__ void scale_kernel(double2* x, int64_t n, double ar, double ai) {
   }
 }
 
+// FP64 complex -> FP32 complex (round to nearest), the storage of the mixed precisions' operands
+__global__ void to_f32_kernel(const double2* __restrict__ src, float2* __restrict__ dst, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = i; k < n; k += stride) {
+    const double2 v = src[k];
+    dst[k] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
 }  // namespace
 
 void dev_set_device(int device) { check(hipSetDevice(device), "hipSetDevice"); }
@@ -253,6 +263,15 @@ void launch_scale(cplx* x, int64_t n, cplx alpha, void* stream) {
   hipLaunchKernelGGL(scale_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, (double2*)x, n, alpha.x,
                      alpha.y);
   check(hipGetLastError(), "scale launch");
+}
+
+void launch_to_f32(const cplx* src, void* dst, int64_t n, void* stream) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, (const double2*)src,
+                     (float2*)dst, n);
+  check(hipGetLastError(), "to_f32 launch");
 }
 
 void dev_sync(void* stream) { check(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize"); }

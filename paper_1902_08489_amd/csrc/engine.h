@@ -154,6 +154,10 @@ struct tdmps_ctx_s {
   // wall-clock counters measure device time (at the cost of host / device overlap).
   bool phase_sync = false;
   bool timing = false;
+  // FP32 / BF16-split H_eff applies keep their operands and the T intermediate in FP32 storage
+  // (converted once per plan; environment variable TDMPS_MIXED_STORAGE=0 at context creation
+  // keeps them in FP64 and converts while staging tiles)
+  bool mixed_storage = true;
 };
 
 struct tdmps_mps_s {
@@ -261,6 +265,8 @@ struct GemmPlan {
   // with an arena, the split-K workspace and the tables are placed in it and the upload waits
   // for its completion (nothing is allocated)
   Arena* arena = nullptr;
+  // operands A and B of every segment are FP32 complex (the mixed precisions' storage)
+  bool ops32 = false;
   void finalize(Ctx* ctx, int precision);
   // batched: one grouped launch per tile shape (default); else one launch per task (the
   // per-block baseline the grouped launch is compared with)
@@ -330,7 +336,14 @@ struct HeffPlan {
   // T stage: p1 stacked over runs, p1b products of blocks shared by a run (combined into the
   // channels' rows by the share pass); p2 final stage
   GemmPlan p1, p1b, p2;
-  DevBuf T, X;  // T intermediate; products of shared blocks
+  DevBuf T, X;  // T intermediate (FP32 complex with ops32); products of shared blocks (FP64)
+  // FP32 storage of the mixed precisions: FP32 copies of the environment operators (made when
+  // the plan is built) and of theta_in (made by every launch)
+  bool ops32 = false;
+  std::vector<DevBuf> shadows;
+  DevBuf theta32;
+  const cplx* theta_in = nullptr;
+  int64_t theta_size = 0;
   std::vector<double> coef_host;
   std::vector<ShareTask> share_host;  // uploaded with p1b's tables: [tasks][coefficients]
   int64_t share_max_blk = 0;

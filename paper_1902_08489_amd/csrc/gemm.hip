@@ -39,12 +39,14 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 
 // Position in the flattened (segment, channel, k-chunk) steps of one task.  The segment
 // descriptor is read only when the cursor enters a new segment; a k step only moves k0.
+// E: operand element type (double2 = FP64 complex storage, float2 = FP32 complex storage).
+template <typename E>
 struct Cursor {
   const GemmSeg* segs;
   int s, se, r, k0, K, nred;
   int64_t lda, ldb, rsA, rsB;
-  const double2* A;  // operands of channel r of the current segment
-  const double2* B;
+  const E* A;  // operands of channel r of the current segment
+  const E* B;
   double2 alpha;
   bool tA, cA, tB, cB;
 
@@ -58,8 +60,8 @@ struct Cursor {
       ldb = S.ldb;
       rsA = S.rsA;
       rsB = S.rsB;
-      A = (const double2*)S.A + bidx * S.bsA;
-      B = (const double2*)S.B + bidx * S.bsB;
+      A = (const E*)S.A + bidx * S.bsA;
+      B = (const E*)S.B + bidx * S.bsB;
       alpha = make_double2(S.alpha.x, S.alpha.y);
       tA = S.opA == OP_T || S.opA == OP_C;
       cA = S.opA == OP_C || S.opA == OP_J;
@@ -88,7 +90,16 @@ struct Cursor {
 // Operands are read through global-address-space pointers: generic (flat) loads would also
 // count against the LDS wait counter, so every LDS read of the MFMA loop would wait for the
 // prefetch of the next stage.
-typedef const __attribute__((address_space(1))) double* gptr;
+template <typename E>
+struct GPtr;
+template <>
+struct GPtr<double2> {
+  typedef const __attribute__((address_space(1))) double* type;
+};
+template <>
+struct GPtr<float2> {
+  typedef const __attribute__((address_space(1))) float* type;
+};
 
 // Element -> thread mapping of the B stage, whatever the operand's storage: BMAP_N puts
 // adjacent threads on adjacent columns, BMAP_K on adjacent k.  The LDS layout decides, not
@@ -98,7 +109,7 @@ typedef const __attribute__((address_space(1))) double* gptr;
 // adjacent k are adjacent words (BMAP_K: 39.9 -> 36.8 ms for the whole H_eff).
 enum { BMAP_N = 1, BMAP_K = 2 };
 
-template <int BM, int BN, int BK, int BMAP>
+template <int BM, int BN, int BK, int BMAP, typename E>
 struct Stage {
   // per-thread prefetch registers: ceil(BM*BK/256) A elements and ceil(BK*BN/256) B elements,
   // raw as loaded (conjugation and the segment scale are applied when they are written to LDS,
@@ -107,9 +118,10 @@ struct Stage {
   static constexpr int NB = (BK * BN + 255) / 256;
   static constexpr bool FULLA = BM * BK % 256 == 0;
   static constexpr bool FULLB = BK * BN % 256 == 0;
-  double2 ra[NA], rb[NB];
+  typedef typename GPtr<E>::type gptr;
+  E ra[NA], rb[NB];
 
-  __device__ __forceinline__ void load(const Cursor& c, const GemmTask& T, int m0, int n0, int tid) {
+  __device__ __forceinline__ void load(const Cursor<E>& c, const GemmTask& T, int m0, int n0, int tid) {
     const gptr A = (gptr)c.A;
     const gptr B = (gptr)c.B;
 #pragma unroll
@@ -124,7 +136,7 @@ struct Stage {
         rr = e - kk * BM;
       }
       const int gr = m0 + rr, gk = c.k0 + kk;
-      double2 v = make_double2(0.0, 0.0);
+      E v = {0, 0};
       if ((FULLA || e < BM * BK) && gr < T.m && gk < c.K) {
         const gptr p = A + 2 * (c.tA ? (int64_t)gk * c.lda + gr : (int64_t)gr * c.lda + gk);
         v.x = p[0];
@@ -144,7 +156,7 @@ struct Stage {
         kk = e - cc * BK;
       }
       const int gk = c.k0 + kk, gc = n0 + cc;
-      double2 v = make_double2(0.0, 0.0);
+      E v = {0, 0};
       if ((FULLB || e < BK * BN) && gk < c.K && gc < T.n) {
         const gptr p = B + 2 * (c.tB ? (int64_t)gc * c.ldb + gk : (int64_t)gk * c.ldb + gc);
         v.x = p[0];
@@ -192,10 +204,19 @@ struct Smem<BM, BN, PBF3> {
   __bf16 Bh[2 * BN][40], Bl[2 * BN][40];
 };
 
-__device__ __forceinline__ void split_bf16(double x, __bf16& h, __bf16& l) {
-  const float f = (float)x;
+__device__ __forceinline__ void split_bf16(float f, __bf16& h, __bf16& l) {
   h = (__bf16)f;
   l = (__bf16)(f - (float)h);
+}
+
+__device__ __forceinline__ double2 scale(double2 v, bool conj, double2 alpha) {
+  if (conj) v.y = -v.y;
+  return cmul(v, alpha);
+}
+__device__ __forceinline__ float2 scale(float2 v, bool conj, double2 alpha) {
+  if (conj) v.y = -v.y;
+  const float ar = (float)alpha.x, ai = (float)alpha.y;
+  return make_float2(v.x * ar - v.y * ai, v.x * ai + v.y * ar);
 }
 
 // two bf16 as one 32-bit LDS word (the first at the lower address)
@@ -203,14 +224,17 @@ __device__ __forceinline__ uint32_t pack_bf16(__bf16 lo, __bf16 hi) {
   return (uint32_t)__builtin_bit_cast(unsigned short, lo) | ((uint32_t)__builtin_bit_cast(unsigned short, hi) << 16);
 }
 
-template <int BM, int BN, int PREC>
+// S32: operands stored as FP32 complex (FP32 and BF16-split precisions)
+template <int BM, int BN, int PREC, bool S32>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void gemm_kernel(const GemmTask* __restrict__ tasks,
                                                    const GemmSeg* __restrict__ segs,
                                                    const int32_t* __restrict__ tile_task, int64_t total_tiles,
                                                    int64_t tile_offset) {
   constexpr int BK = PREC == P64 ? 8 : 16;  // complex k per LDS stage (FP64: fewer live registers)
   constexpr int BMAP = PREC == PBF3 ? BMAP_K : BMAP_N;
-  typedef Stage<BM, BN, BK, BMAP> St;
+  static_assert(!(S32 && PREC == P64), "FP64 products read FP64 operands");
+  typedef typename std::conditional<S32, float2, double2>::type E;
+  typedef Stage<BM, BN, BK, BMAP, E> St;
   constexpr int WM = BM / 2;                 // complex rows per wave
   constexpr int WN = BN / 2;                 // complex columns per wave
   constexpr int TM = WM / 16;                // 16x16 MFMA tiles along m
@@ -245,7 +269,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
   St st;
-  Cursor cur;
+  Cursor<E> cur;
   cur.segs = segs;
   cur.s = T.seg0;
   cur.se = T.seg0 + T.nseg;
@@ -267,9 +291,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
           kk = e / BM;
           rr = e - kk * BM;
         }
-        double2 v = st.ra[q];
-        if (cur.cA) v.y = -v.y;
-        v = cmul(v, cur.alpha);
+        const E v = scale(st.ra[q], cur.cA, cur.alpha);
         if constexpr (PREC == P64) {
           *(double2*)&sm.A[rr][2 * kk] = v;
         } else if constexpr (PREC == P32) {
@@ -294,7 +316,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
           cc = e / BK;
           kk = e - cc * BK;
         }
-        double2 v = st.rb[q];
+        E v = st.rb[q];
         if (cur.cB) v.y = -v.y;
         if constexpr (PREC == P64) {
           *(double2*)&sm.B[2 * kk][2 * cc] = v;
@@ -317,7 +339,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
       }
     }
     __syncthreads();
-    Cursor nx = cur;
+    Cursor<E> nx = cur;
     const bool more = nx.advance(bidx, BK);
     if (more) st.load(nx, T, m0, n0, tid);
     if constexpr (PREC == PBF3) {
@@ -368,7 +390,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
   // holds row l/16 + 4e of a 16x16 tile for the f64 MFMA and row 4(l/16) + e for the f32
   // and bf16 MFMAs; column l%16 in all cases.
   typedef __attribute__((address_space(1))) double* gout;
+  typedef __attribute__((address_space(1))) float* gout32;
+  const bool out32 = T.flags & GEMM_OUT32;  // uniform over the workgroup
   const gout C = (gout)(T.C + bidx * T.bsC);
+  const gout32 C32 = (gout32)((float2*)T.C + bidx * T.bsC);
   const bool accum = T.flags & GEMM_ACCUM;
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
@@ -388,7 +413,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         for (int e = 0; e < 4; ++e) {
           const int row = PREC == P64 ? lq + 4 * e : 4 * lq + e;
           const int gr = m0 + wm + i * 16 + row;
-          if (gr < T.m && gc < T.n) old[j][e] = C[2 * ((int64_t)gr * T.ldc + gc) + (rc & 1)];
+          if (gr < T.m && gc < T.n) {
+            const int64_t at = 2 * ((int64_t)gr * T.ldc + gc) + (rc & 1);
+            old[j][e] = out32 ? (double)C32[at] : C[at];
+          }
         }
       }
     }
@@ -400,7 +428,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
       for (int e = 0; e < 4; ++e) {
         const int row = PREC == P64 ? lq + 4 * e : 4 * lq + e;
         const int gr = m0 + wm + i * 16 + row;
-        if (gr < T.m && gc < T.n) C[2 * ((int64_t)gr * T.ldc + gc) + (rc & 1)] = old[j][e] + (double)acc[i][j][e];
+        if (gr < T.m && gc < T.n) {
+          const int64_t at = 2 * ((int64_t)gr * T.ldc + gc) + (rc & 1);
+          if (out32)
+            C32[at] = (float)(old[j][e] + (double)acc[i][j][e]);
+          else
+            C[at] = old[j][e] + (double)acc[i][j][e];
+        }
       }
     }
   }
@@ -421,13 +455,23 @@ __global__ __launch_bounds__(256) void reduce_kernel(const ReduceTask* __restric
       s.y += v.y;
     }
     const int r = (int)(e / t.n), c = (int)(e - (int64_t)r * t.n);
-    double2* d = C + (int64_t)r * t.ldc + c;
-    if (t.accum) {
-      double2 o = *d;
-      s.x += o.x;
-      s.y += o.y;
+    if (t.out32) {
+      float2* d = (float2*)t.C + (int64_t)r * t.ldc + c;
+      if (t.accum) {
+        const float2 o = *d;
+        s.x += o.x;
+        s.y += o.y;
+      }
+      *d = make_float2((float)s.x, (float)s.y);
+    } else {
+      double2* d = C + (int64_t)r * t.ldc + c;
+      if (t.accum) {
+        double2 o = *d;
+        s.x += o.x;
+        s.y += o.y;
+      }
+      *d = s;
     }
-    *d = s;
   }
 }
 
@@ -455,33 +499,39 @@ int gemm_tile_n(int cfg) { return CFG_N[cfg]; }
 
 template <int BM, int BN>
 void launch_cfg(const GemmTask* tasks, const GemmSeg* segs, const int32_t* tile_task, int64_t total_tiles, int precision,
-                hipStream_t stream, int64_t off) {
+                hipStream_t stream, int64_t off, bool ops32) {
   const int64_t grid = 8 * ((total_tiles + 7) / 8);
   TDMPS_REQUIRE(grid < ((int64_t)1 << 31), TDMPS_ERR_ARG, "too many GEMM tiles in one launch");
+  TDMPS_REQUIRE(!ops32 || precision == TDMPS_FP32 || precision == TDMPS_BF16X3, TDMPS_ERR_ARG,
+                "FP32 operand storage needs the FP32 or BF16-split precision");
   dim3 g((unsigned)grid), block(256);
-  if (precision == TDMPS_FP32)
-    hipLaunchKernelGGL((gemm_kernel<BM, BN, P32>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
+  if (precision == TDMPS_FP32 && ops32)
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, P32, true>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
+  else if (precision == TDMPS_FP32)
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, P32, false>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
+  else if (precision == TDMPS_BF16X3 && ops32)
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, PBF3, true>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
   else if (precision == TDMPS_BF16X3)
-    hipLaunchKernelGGL((gemm_kernel<BM, BN, PBF3>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, PBF3, false>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
   else
-    hipLaunchKernelGGL((gemm_kernel<BM, BN, P64>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, P64, false>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
 }
 
 void launch_gemm(const GemmTask* tasks, const GemmSeg* segs, const int32_t* tile_task, int64_t total_tiles, int cfg,
-                 int precision, void* stream, int64_t off) {
+                 int precision, void* stream, int64_t off, bool ops32) {
   if (total_tiles <= 0) return;
   hipStream_t s = (hipStream_t)stream;
   switch (cfg) {
-    case 0: launch_cfg<64, 64>(tasks, segs, tile_task, total_tiles, precision, s, off); break;
-    case 1: launch_cfg<32, 32>(tasks, segs, tile_task, total_tiles, precision, s, off); break;
-    case 2: launch_cfg<128, 32>(tasks, segs, tile_task, total_tiles, precision, s, off); break;
-    case 3: launch_cfg<64, 48>(tasks, segs, tile_task, total_tiles, precision, s, off); break;
-    case 4: launch_cfg<96, 48>(tasks, segs, tile_task, total_tiles, precision, s, off); break;
-    case 5: launch_cfg<128, 48>(tasks, segs, tile_task, total_tiles, precision, s, off); break;
-    case 6: launch_cfg<32, 48>(tasks, segs, tile_task, total_tiles, precision, s, off); break;
-    case 7: launch_cfg<96, 64>(tasks, segs, tile_task, total_tiles, precision, s, off); break;
-    case 8: launch_cfg<96, 32>(tasks, segs, tile_task, total_tiles, precision, s, off); break;
-    case 9: launch_cfg<64, 32>(tasks, segs, tile_task, total_tiles, precision, s, off); break;
+    case 0: launch_cfg<64, 64>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32); break;
+    case 1: launch_cfg<32, 32>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32); break;
+    case 2: launch_cfg<128, 32>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32); break;
+    case 3: launch_cfg<64, 48>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32); break;
+    case 4: launch_cfg<96, 48>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32); break;
+    case 5: launch_cfg<128, 48>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32); break;
+    case 6: launch_cfg<32, 48>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32); break;
+    case 7: launch_cfg<96, 64>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32); break;
+    case 8: launch_cfg<96, 32>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32); break;
+    case 9: launch_cfg<64, 32>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32); break;
     default: throw Error(TDMPS_ERR_ARG, "bad GEMM tile configuration");
   }
   check(hipGetLastError(), "gemm launch");

@@ -17,8 +17,11 @@ struct cplx {
 //   C_b = [C_b +] sum_seg alpha_seg * sum_{r < nred} op(A_seg + b*bsA + r*rsA) op(B_seg + b*bsB + r*rsB)
 // with op in {N, T, C (conjugate transpose), J (conjugate)}; op(A) is m x k, op(B) k x n,
 // all row-major with leading dimensions lda, ldb, ldc (in complex elements).
+// Element storage: FP64 complex (16 bytes) by default.  A launch with FP32 operands (the mixed
+// precisions' storage) reads A and B as FP32 complex (8 bytes; pointers and strides still count
+// complex elements); GEMM_OUT32 makes a task write C as FP32 complex.
 enum { OP_N = 0, OP_T = 1, OP_C = 2, OP_J = 3 };
-enum { GEMM_ACCUM = 1 };
+enum { GEMM_ACCUM = 1, GEMM_OUT32 = 2 };
 
 struct GemmTask {
   cplx* C;
@@ -37,11 +40,12 @@ struct GemmSeg {
   cplx alpha;
 };
 
-// Split-K partial sums: C (+)= sum_{q < nparts} parts[q] (each part m x n, contiguous).
+// Split-K partial sums: C (+)= sum_{q < nparts} parts[q] (each part m x n, contiguous, FP64);
+// out32: C is FP32 complex.
 struct ReduceTask {
   cplx* C;
   const cplx* parts;
-  int32_t m, n, ldc, nparts, accum;
+  int32_t m, n, ldc, nparts, accum, out32;
 };
 
 // ---------------------------------------------------------------- shared-block combination
@@ -50,11 +54,11 @@ struct ReduceTask {
 // coefficients (nq <= SHARE_MAXQ).
 constexpr int SHARE_MAXQ = 8;
 struct ShareTask {
-  cplx* T;
+  cplx* T;  // FP32 complex if out32
   const cplx* X;
   int64_t coff;  // first coefficient of the task in the coefficient array of the launch
   int64_t blk;
-  int32_t nrun, nq, accum, pad;
+  int32_t nrun, nq, accum, out32;
 };
 
 // ---------------------------------------------------------------- strided block copies
@@ -134,8 +138,9 @@ void* noalloc_scratch(int device, size_t* cap);
 
 // launchers (all asynchronous on `stream`)
 // Runs tiles tile_offset .. tile_offset + total_tiles - 1 of the tile table.
+// ops32: A and B are FP32 complex (FP32 and BF16-split precisions only).
 void launch_gemm(const GemmTask* tasks, const GemmSeg* segs, const int32_t* tile_task, int64_t total_tiles, int cfg,
-                 int precision, void* stream, int64_t tile_offset = 0);
+                 int precision, void* stream, int64_t tile_offset = 0, bool ops32 = false);
 void launch_reduce(const ReduceTask* tasks, int ntasks, void* stream);
 constexpr int GEMM_NCFG = 10;  // tile shape configurations of launch_gemm
 int gemm_tile_m(int cfg);
@@ -152,6 +157,8 @@ void launch_svd_round(const SvdMat* mats, int nmats, int64_t total_pairs, int ro
                       const int32_t* prev_counter, int waves, void* stream);
 void launch_svd_norms(const SvdMat* mats, int nmats, int max_k, double* sigma_out, void* stream);
 void launch_scale(cplx* x, int64_t n, cplx alpha, void* stream);
+// dst[e] = (FP32 complex) src[e], e < n (dst: 8 bytes per element)
+void launch_to_f32(const cplx* src, void* dst, int64_t n, void* stream);
 // QR preconditioning of the Jacobi SVD: factor panel j0 (one workgroup per matrix); apply
 // panel j0 to the trailing columns of G (mode 0) or Q's panel to B (mode 1) over total_blocks
 // = sum ceil(k / QR_PANEL) column blocks; X = R^H; finish: B = [V; 0], X <- X Sigma^{-1} with

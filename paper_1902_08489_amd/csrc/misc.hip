@@ -345,7 +345,14 @@ __global__ __launch_bounds__(256) void share_kernel(const ShareTask* __restrict_
 #pragma unroll
     for (int q = 0; q < SHARE_MAXQ; ++q) x[q] = q < t.nq ? X[q * t.blk + e] : make_double2(0.0, 0.0);
     for (int j = 0; j < t.nrun; ++j) {
-      double2 s = t.accum ? T[j * t.blk + e] : make_double2(0.0, 0.0);
+      float2* T32 = (float2*)t.T + j * t.blk + e;  // out32: the FP32 storage of the mixed precisions
+      double2 s = make_double2(0.0, 0.0);
+      if (t.accum) {
+        if (t.out32)
+          s = make_double2(T32->x, T32->y);
+        else
+          s = T[j * t.blk + e];
+      }
 #pragma unroll
       for (int q = 0; q < SHARE_MAXQ; ++q)
         if (q < t.nq) {
@@ -353,7 +360,10 @@ __global__ __launch_bounds__(256) void share_kernel(const ShareTask* __restrict_
           s.x += c * x[q].x;
           s.y += c * x[q].y;
         }
-      T[j * t.blk + e] = s;
+      if (t.out32)
+        *T32 = make_float2((float)s.x, (float)s.y);
+      else
+        T[j * t.blk + e] = s;
     }
   }
 }

@@ -208,6 +208,7 @@ void GemmPlan::finalize(Ctx* ctx, int precision) {
   // KSPLIT complex k; parts write private partial outputs that a reduction kernel adds in
   // a fixed order (deterministic, no atomics).
   const int64_t KSPLIT = 1024;
+  const int64_t esz = ops32 ? 8 : (int64_t)sizeof(cplx);  // bytes per operand element
   std::vector<GemmTask> out = t_task_pool.take();
   std::vector<GemmSeg> nsegs = t_seg_pool.take();
   struct Scratch {
@@ -244,6 +245,7 @@ void GemmPlan::finalize(Ctx* ctx, int precision) {
     rt.n = t.n;
     rt.ldc = t.ldc;
     rt.accum = (t.flags & GEMM_ACCUM) ? 1 : 0;
+    rt.out32 = (t.flags & GEMM_OUT32) ? 1 : 0;
     int64_t base = ws;
     int made = 0;
     GemmTask cur = t;
@@ -269,8 +271,8 @@ void GemmPlan::finalize(Ctx* ctx, int precision) {
         int64_t room = target - acc;
         int take = (int)std::max<int64_t>(1, std::min<int64_t>(g.nred - r, room / std::max(1, g.k)));
         GemmSeg v = g;
-        v.A = g.A + (int64_t)r * g.rsA;
-        v.B = g.B + (int64_t)r * g.rsB;
+        v.A = (const cplx*)((const char*)g.A + (int64_t)r * g.rsA * esz);
+        v.B = (const cplx*)((const char*)g.B + (int64_t)r * g.rsB * esz);
         v.nred = take;
         nsegs.push_back(v);
         cur.nseg++;
@@ -399,14 +401,14 @@ void GemmPlan::launch(Ctx* ctx, int precision, bool batched) {
     if (ntask[cfg] <= 0) continue;
     if (batched) {
       launch_gemm(dtasks[cfg], dsegs, dtile[cfg], ntiles[cfg],
-                  cfg, precision, ctx->stream, 0);
+                  cfg, precision, ctx->stream, 0, ops32);
     } else {
       // one launch per task: the grid covers the task's own tiles only
       for (size_t t = 0; t < htile_base[cfg].size(); ++t) {
         const int64_t b0 = htile_base[cfg][t];
         const int64_t b1 = t + 1 < htile_base[cfg].size() ? htile_base[cfg][t + 1] : ntiles[cfg];
         launch_gemm(dtasks[cfg], dsegs, dtile[cfg], b1 - b0,
-                    cfg, precision, ctx->stream, b0);
+                    cfg, precision, ctx->stream, b0, ops32);
       }
     }
   }

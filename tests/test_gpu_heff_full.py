@@ -111,6 +111,23 @@ def test_heff_all_outputs_L10_centre_whole_sector(ctx, window, monkeypatch):
     assert n == dim == 52920
 
 
+def test_heff_L10_centre_mixed_precisions_fp64_storage(monkeypatch):
+    """The mixed precisions with FP64 operand storage (conversion while staging tiles; a
+    context created with TDMPS_MIXED_STORAGE=0) give the same bounds on every output, and the
+    default FP32 storage halves the T intermediate (plan counter 3: its bytes)."""
+    T.load()
+    monkeypatch.setenv("TDMPS_MIXED_STORAGE", "0")
+    c64 = T.Context(0)
+    monkeypatch.delenv("TDMPS_MIXED_STORAGE")
+    _run_case(c64, 10, 10, 4, fci.HamiltonianOp, precisions=(T.FP32, T.BF16X3))
+    t_bytes_64 = c64.counters()[3]
+    c32 = T.Context(0)
+    _run_case(c32, 10, 10, 4, fci.HamiltonianOp, precisions=(T.FP32,))
+    t_bytes_32 = c32.counters()[3]
+    print(f"T intermediate: {t_bytes_64:.3e} bytes (FP64 storage), {t_bytes_32:.3e} (FP32 storage)")
+    assert t_bytes_32 * 2 == t_bytes_64
+
+
 @pytest.mark.parametrize("c", [2, 6])
 def test_heff_all_outputs_L10_off_centre(ctx, c):
     """L = 10 bonds (2, 3) and (6, 7): both sides of the switch of the operator automaton at the
