@@ -137,6 +137,8 @@ def main():
     ap.add_argument("--rk4-steps", type=int, default=200)
     ap.add_argument("--checkpoint", type=int, default=20)
     ap.add_argument("--fd", type=int, default=0, help="gradient workload: also central finite differences")
+    ap.add_argument("--backward", type=int, default=1,
+                    help="gradient workload: 0 skips the adjoint pass (a finite-difference-only line)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the contraction path is single-device (multi-GPU sharding over MPO "
@@ -537,10 +539,12 @@ def other_workload(args, progress):
                           args.rk4_steps, args.checkpoint, prm)
         t_fwd = time.perf_counter() - t0
         progress(f"forward {args.rk4_steps} RK4 steps: {t_fwd:.1f} s")
-        t0 = time.perf_counter()
-        g = tr.backward()
-        t_bwd = time.perf_counter() - t0
-        progress(f"backward: {t_bwd:.1f} s")
+        g, t_bwd = None, 0.0
+        if args.backward:
+            t0 = time.perf_counter()
+            g = tr.backward()
+            t_bwd = time.perf_counter() - t0
+            progress(f"backward: {t_bwd:.1f} s")
         fd = None
         if args.fd:
             hA = 1e-4
@@ -549,7 +553,9 @@ def other_workload(args, progress):
             vm = T.Trajectory(H0, h, mu_pq, MU, psi0, A - hA, pulse["omega"], pulse["t_center"], pulse["width"], dt,
                               args.rk4_steps, args.checkpoint, prm).value
             fd = (vp - vm) / (2 * hA)
-        line.update({"metric": f"RK4 forward+adjoint steps/s @L={L} D={D}", "value": args.rk4_steps / (t_fwd + t_bwd),
+            progress(f"finite difference: {fd:.12e}")
+        what = "forward+adjoint" if args.backward else "forward"
+        line.update({"metric": f"RK4 {what} steps/s @L={L} D={D}", "value": args.rk4_steps / (t_fwd + t_bwd),
                      "unit": "steps/s", "ms_per_step": (t_fwd + t_bwd) / args.rk4_steps * 1e3,
                      "dtype": args.precision,
                      "config": {"workload": f"field-driven RK4, L={L} N={N0 - 1} D={D}, {args.rk4_steps} steps of {dt}, "
@@ -557,7 +563,7 @@ def other_workload(args, progress):
                                             f"A = {A}, {args.sweeps} sweep(s) per fit"},
                      "forward_s": t_fwd, "backward_s": t_bwd, "dipole": tr.value, "dD_dA": g,
                      "finite_difference": fd,
-                     "rel_diff_vs_fd": None if fd is None else abs(g - fd) / max(abs(fd), 1e-300)})
+                     "rel_diff_vs_fd": None if fd is None or g is None else abs(g - fd) / max(abs(fd), 1e-300)})
     print(json.dumps(line), flush=True)
 
 

@@ -229,10 +229,13 @@ SideOps build_ops(Contractor& C, const Env& E, const MpoHost& W, int site, bool 
     }
   }
   if (sk->groups.empty()) return ops;
-  // one real-coefficient GEMM over the source channels per group and ket sector
+  // one real-coefficient GEMM over the source channels per group and ket sector (real-A
+  // products: the coefficients are the real parts of the uploaded matrices)
   const cplx* dw = sk->wmat->c();
   GemmPlan local;
   GemmPlan& plan = ext ? *ext : local;
+  TDMPS_REQUIRE(plan.real_a || plan.task_count() == 0, TDMPS_ERR_NUMERIC, "internal: premix plan with complex products");
+  plan.real_a = true;
   const Blocks& eb = E.b;
   for (const auto& p : sk->pend) {
     const StackGroup& sg = ops.mix->grp[p.g];

@@ -267,6 +267,9 @@ struct GemmPlan {
   Arena* arena = nullptr;
   // operands A and B of every segment are FP32 complex (the mixed precisions' storage)
   bool ops32 = false;
+  // every segment's A is real-valued (premix coefficients): FP64 real-A products, 4 flops per
+  // multiply-add executed (set before the first add_seg)
+  bool real_a = false;
   void finalize(Ctx* ctx, int precision);
   // batched: one grouped launch per tile shape (default); else one launch per task (the
   // per-block baseline the grouped launch is compared with)

@@ -167,6 +167,50 @@ struct Stage {
   }
 };
 
+// Staging of a real-A product (FP64 only): C = A B with A real (the real parts of the stored
+// complex A, non-transposed) and B complex, non-transposed.  One LDS stage then covers 2 * BK
+// values of k: the A' rows hold A's real values at the realified-k positions and B' row k holds
+// (Re, Im) of B's complex row k, so the same MFMA loop forms C' = A' B' = the interleaved
+// complex result with half the products of the complex form.
+template <int BM, int BN, int BK>
+struct StageRA {
+  static constexpr int KR = 2 * BK;  // k values per stage
+  static constexpr int NA = (BM * KR + 255) / 256;
+  static constexpr int NB = (KR * BN + 255) / 256;
+  static constexpr bool FULLA = BM * KR % 256 == 0;
+  static constexpr bool FULLB = KR * BN % 256 == 0;
+  typedef const __attribute__((address_space(1))) double* gptr;
+  double ra[NA];
+  double2 rb[NB];
+
+  __device__ __forceinline__ void load(const Cursor<double2>& c, const GemmTask& T, int m0, int n0, int tid) {
+    const gptr A = (gptr)c.A;
+    const gptr B = (gptr)c.B;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + q * 256;
+      const int rr = e / KR, kk = e - rr * KR;
+      const int gr = m0 + rr, gk = c.k0 + kk;
+      double v = 0.0;
+      if ((FULLA || e < BM * KR) && gr < T.m && gk < c.K) v = A[2 * ((int64_t)gr * c.lda + gk)];
+      ra[q] = v;
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + q * 256;
+      const int kk = e / BN, cc = e - kk * BN;
+      const int gk = c.k0 + kk, gc = n0 + cc;
+      double2 v = make_double2(0.0, 0.0);
+      if ((FULLB || e < KR * BN) && gk < c.K && gc < T.n) {
+        const gptr p = B + 2 * ((int64_t)gk * c.ldb + gc);
+        v.x = p[0];
+        v.y = p[1];
+      }
+      rb[q] = v;
+    }
+  }
+};
+
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
@@ -224,8 +268,8 @@ __device__ __forceinline__ uint32_t pack_bf16(__bf16 lo, __bf16 hi) {
   return (uint32_t)__builtin_bit_cast(unsigned short, lo) | ((uint32_t)__builtin_bit_cast(unsigned short, hi) << 16);
 }
 
-// S32: operands stored as FP32 complex (FP32 and BF16-split precisions)
-template <int BM, int BN, int PREC, bool S32>
+// S32: operands stored as FP32 complex (FP32 and BF16-split precisions); RA: real A (FP64)
+template <int BM, int BN, int PREC, bool S32, bool RA>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void gemm_kernel(const GemmTask* __restrict__ tasks,
                                                    const GemmSeg* __restrict__ segs,
                                                    const int32_t* __restrict__ tile_task, int64_t total_tiles,
@@ -233,8 +277,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
   constexpr int BK = PREC == P64 ? 8 : 16;  // complex k per LDS stage (FP64: fewer live registers)
   constexpr int BMAP = PREC == PBF3 ? BMAP_K : BMAP_N;
   static_assert(!(S32 && PREC == P64), "FP64 products read FP64 operands");
+  static_assert(!RA || (PREC == P64 && !S32), "real-A products are FP64");
   typedef typename std::conditional<S32, float2, double2>::type E;
-  typedef Stage<BM, BN, BK, BMAP, E> St;
+  typedef typename std::conditional<RA, StageRA<BM, BN, BK>, Stage<BM, BN, BK, BMAP, E>>::type St;
+  constexpr int KSTEP = RA ? 2 * BK : BK;  // k values per LDS stage
   constexpr int WM = BM / 2;                 // complex rows per wave
   constexpr int WN = BN / 2;                 // complex columns per wave
   constexpr int TM = WM / 16;                // 16x16 MFMA tiles along m
@@ -277,7 +323,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
   if (have) st.load(cur, T, m0, n0, tid);
   while (have) {
     // registers -> LDS in the precision's layout
-    {
+    if constexpr (RA) {
+#pragma unroll
+      for (int q = 0; q < St::NA; ++q) {
+        const int e = tid + q * 256;
+        if (!St::FULLA && e >= BM * St::KR) continue;
+        const int rr = e / St::KR, kk = e - rr * St::KR;
+        sm.A[rr][kk] = st.ra[q] * cur.alpha.x;
+      }
+#pragma unroll
+      for (int q = 0; q < St::NB; ++q) {
+        const int e = tid + q * 256;
+        if (!St::FULLB && e >= St::KR * BN) continue;
+        const int kk = e / BN, cc = e - kk * BN;
+        *(double2*)&sm.B[kk][2 * cc] = st.rb[q];
+      }
+    } else {
       const bool transA = cur.tA;
 #pragma unroll
       for (int q = 0; q < St::NA; ++q) {
@@ -340,7 +401,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     }
     __syncthreads();
     Cursor<E> nx = cur;
-    const bool more = nx.advance(bidx, BK);
+    const bool more = nx.advance(bidx, KSTEP);
     if (more) st.load(nx, T, m0, n0, tid);
     if constexpr (PREC == PBF3) {
       bf8 ah[TM], al[TM];
@@ -499,39 +560,43 @@ int gemm_tile_n(int cfg) { return CFG_N[cfg]; }
 
 template <int BM, int BN>
 void launch_cfg(const GemmTask* tasks, const GemmSeg* segs, const int32_t* tile_task, int64_t total_tiles, int precision,
-                hipStream_t stream, int64_t off, bool ops32) {
+                hipStream_t stream, int64_t off, bool ops32, bool real_a) {
   const int64_t grid = 8 * ((total_tiles + 7) / 8);
   TDMPS_REQUIRE(grid < ((int64_t)1 << 31), TDMPS_ERR_ARG, "too many GEMM tiles in one launch");
   TDMPS_REQUIRE(!ops32 || precision == TDMPS_FP32 || precision == TDMPS_BF16X3, TDMPS_ERR_ARG,
                 "FP32 operand storage needs the FP32 or BF16-split precision");
+  TDMPS_REQUIRE(!real_a || (precision == TDMPS_FP64 && !ops32), TDMPS_ERR_ARG, "real-A products are FP64");
   dim3 g((unsigned)grid), block(256);
-  if (precision == TDMPS_FP32 && ops32)
-    hipLaunchKernelGGL((gemm_kernel<BM, BN, P32, true>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
+  if (real_a)
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, P64, false, true>), g, block, 0, stream, tasks, segs, tile_task, total_tiles,
+                       off);
+  else if (precision == TDMPS_FP32 && ops32)
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, P32, true, false>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
   else if (precision == TDMPS_FP32)
-    hipLaunchKernelGGL((gemm_kernel<BM, BN, P32, false>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, P32, false, false>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
   else if (precision == TDMPS_BF16X3 && ops32)
-    hipLaunchKernelGGL((gemm_kernel<BM, BN, PBF3, true>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, PBF3, true, false>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
   else if (precision == TDMPS_BF16X3)
-    hipLaunchKernelGGL((gemm_kernel<BM, BN, PBF3, false>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, PBF3, false, false>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
   else
-    hipLaunchKernelGGL((gemm_kernel<BM, BN, P64, false>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, P64, false, false>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
 }
 
 void launch_gemm(const GemmTask* tasks, const GemmSeg* segs, const int32_t* tile_task, int64_t total_tiles, int cfg,
-                 int precision, void* stream, int64_t off, bool ops32) {
+                 int precision, void* stream, int64_t off, bool ops32, bool real_a) {
   if (total_tiles <= 0) return;
   hipStream_t s = (hipStream_t)stream;
   switch (cfg) {
-    case 0: launch_cfg<64, 64>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32); break;
-    case 1: launch_cfg<32, 32>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32); break;
-    case 2: launch_cfg<128, 32>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32); break;
-    case 3: launch_cfg<64, 48>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32); break;
-    case 4: launch_cfg<96, 48>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32); break;
-    case 5: launch_cfg<128, 48>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32); break;
-    case 6: launch_cfg<32, 48>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32); break;
-    case 7: launch_cfg<96, 64>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32); break;
-    case 8: launch_cfg<96, 32>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32); break;
-    case 9: launch_cfg<64, 32>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32); break;
+    case 0: launch_cfg<64, 64>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32, real_a); break;
+    case 1: launch_cfg<32, 32>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32, real_a); break;
+    case 2: launch_cfg<128, 32>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32, real_a); break;
+    case 3: launch_cfg<64, 48>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32, real_a); break;
+    case 4: launch_cfg<96, 48>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32, real_a); break;
+    case 5: launch_cfg<128, 48>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32, real_a); break;
+    case 6: launch_cfg<32, 48>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32, real_a); break;
+    case 7: launch_cfg<96, 64>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32, real_a); break;
+    case 8: launch_cfg<96, 32>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32, real_a); break;
+    case 9: launch_cfg<64, 32>(tasks, segs, tile_task, total_tiles, precision, s, off, ops32, real_a); break;
     default: throw Error(TDMPS_ERR_ARG, "bad GEMM tile configuration");
   }
   check(hipGetLastError(), "gemm launch");

@@ -138,9 +138,11 @@ void* noalloc_scratch(int device, size_t* cap);
 
 // launchers (all asynchronous on `stream`)
 // Runs tiles tile_offset .. tile_offset + total_tiles - 1 of the tile table.
-// ops32: A and B are FP32 complex (FP32 and BF16-split precisions only).
+// ops32: A and B are FP32 complex (FP32 and BF16-split precisions only).  real_a: A is real-valued
+// (the real parts of the stored complex A are read, A and B not transposed, alpha real; FP64
+// only): half the matrix-unit products of the complex form.
 void launch_gemm(const GemmTask* tasks, const GemmSeg* segs, const int32_t* tile_task, int64_t total_tiles, int cfg,
-                 int precision, void* stream, int64_t tile_offset = 0, bool ops32 = false);
+                 int precision, void* stream, int64_t tile_offset = 0, bool ops32 = false, bool real_a = false);
 void launch_reduce(const ReduceTask* tasks, int ntasks, void* stream);
 constexpr int GEMM_NCFG = 10;  // tile shape configurations of launch_gemm
 int gemm_tile_m(int cfg);

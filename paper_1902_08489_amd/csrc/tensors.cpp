@@ -189,7 +189,7 @@ void GemmPlan::add_seg(const cplx* A, int64_t bsA, int64_t rsA, int lda, int opA
   segs.push_back(s);
   GemmTask& t = tasks.back();
   t.nseg++;
-  flops += 8.0 * t.m * (double)t.n * k * nred * t.nbatch;
+  flops += (real_a ? 4.0 : 8.0) * t.m * (double)t.n * k * nred * t.nbatch;
 }
 
 void GemmPlan::finalize(Ctx* ctx, int precision) {
@@ -301,9 +301,12 @@ void GemmPlan::finalize(Ctx* ctx, int precision) {
   static const double eff[GEMM_NCFG] = {1.0, 0.92, 0.9, 0.96, 0.82, 0.8, 0.94, 0.85, 0.8, 0.97};
   const TileTable* tt_tab = (precision >= 0 && precision < 3 && ctx->tune[precision].valid) ? &ctx->tune[precision]
                                                                                            : nullptr;
+  // real-A products (premix) take the cost model over the shapes whose real-A kernels keep
+  // every value in registers (128 x 48 and 96 x 64 spill there)
+  auto usable = [&](int c) { return !real_a || (gemm_tile_m(c) * gemm_tile_n(c) < 6144); };
   auto pick = [&](const GemmTask& t) {
-    if (ctx->tile_cfg >= 0) return ctx->tile_cfg;
-    if (tt_tab) {
+    if (ctx->tile_cfg >= 0 && usable(ctx->tile_cfg)) return ctx->tile_cfg;
+    if (tt_tab && !real_a) {
       int64_t k = 0;
       for (int s = t.seg0; s < t.seg0 + t.nseg; ++s) k += (int64_t)nsegs[s].nred * nsegs[s].k;
       return (int)tt_tab->cfg[tile_bucket(t.m)][tile_bucket(t.n)][tile_kbucket(k)];
@@ -311,6 +314,7 @@ void GemmPlan::finalize(Ctx* ctx, int precision) {
     int best = 0;
     double bc = 1e300;
     for (int c = 0; c < NCFG; ++c) {
+      if (!usable(c)) continue;
       const int bm = gemm_tile_m(c), bn = gemm_tile_n(c);
       const double tiles = (double)((t.m + bm - 1) / bm) * ((t.n + bn - 1) / bn);
       const double cost = tiles * bm * bn / eff[c];
@@ -401,14 +405,14 @@ void GemmPlan::launch(Ctx* ctx, int precision, bool batched) {
     if (ntask[cfg] <= 0) continue;
     if (batched) {
       launch_gemm(dtasks[cfg], dsegs, dtile[cfg], ntiles[cfg],
-                  cfg, precision, ctx->stream, 0, ops32);
+                  cfg, precision, ctx->stream, 0, ops32, real_a);
     } else {
       // one launch per task: the grid covers the task's own tiles only
       for (size_t t = 0; t < htile_base[cfg].size(); ++t) {
         const int64_t b0 = htile_base[cfg][t];
         const int64_t b1 = t + 1 < htile_base[cfg].size() ? htile_base[cfg][t + 1] : ntiles[cfg];
         launch_gemm(dtasks[cfg], dsegs, dtile[cfg], b1 - b0,
-                    cfg, precision, ctx->stream, b0, ops32);
+                    cfg, precision, ctx->stream, b0, ops32, real_a);
       }
     }
   }
