@@ -532,6 +532,7 @@ def other_workload(args, progress):
         psi0 = T.MPS.from_determinant(ctx, synth.ionized_determinant(L, N0))
         prm = T.fit_params(Dmax=D, n_sweeps=args.sweeps, precision=PREC[args.precision])
         pulse = dict(omega=1.0, t_center=2.0, width=0.5)
+        os.environ["TDMPS_PROGRESS"] = "1"  # the library prints one line per checkpoint interval
         A = 0.01
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -19,6 +19,8 @@
 // map, with an error of the order of the truncation, and does not include the variation of
 // the kept singular subspaces with the amplitude.
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 #include "pulse.h"
 
@@ -55,10 +57,15 @@ Mps* combine(Contractor& C, const std::vector<FitTerm>& terms, const tdmps_fit_p
 void pulse_forward(Contractor& C, PulseRun& r, const Mps* psi0) {
   TDMPS_REQUIRE(r.nsteps >= 1 && r.every >= 1, TDMPS_ERR_ARG, "need nsteps >= 1 and checkpoint interval >= 1");
   r.ckpt.clear();
+  // optional progress lines on stderr (TDMPS_PROGRESS set): one per checkpoint interval
+  const bool progress = std::getenv("TDMPS_PROGRESS") != nullptr;
+  const double t0 = wall_seconds();
   std::unique_ptr<Mps> psi(mps_clone(psi0));
   for (int n = 0; n < r.nsteps; ++n) {
     if (n % r.every == 0) r.ckpt.emplace_back(mps_clone(psi.get()));
     psi.reset(step(C, r, psi.get(), n));
+    if (progress && ((n + 1) % r.every == 0 || n + 1 == r.nsteps))
+      std::fprintf(stderr, "pulse: forward step %d of %d after %.1f s\n", n + 1, r.nsteps, wall_seconds() - t0);
   }
   r.last = std::move(psi);
   r.norm2 = overlap(C, r.last.get(), r.last.get()).x;
@@ -75,7 +82,12 @@ double pulse_backward(Contractor& C, PulseRun& r) {
   double grad = 0;
   const cplx adj{0.0, dt};  // A_s^H = +i dt H(t_s)
   const cplx fwd{0.0, -dt};
+  const bool progress = std::getenv("TDMPS_PROGRESS") != nullptr;
+  const double t0 = wall_seconds();
   for (int seg = (int)r.ckpt.size() - 1; seg >= 0; --seg) {
+    if (progress)
+      std::fprintf(stderr, "pulse: adjoint segment %d of %d after %.1f s\n", (int)r.ckpt.size() - seg,
+                   (int)r.ckpt.size(), wall_seconds() - t0);
     const int n0 = seg * r.every, n1 = std::min(r.nsteps, n0 + r.every);
     // recompute psi_n0 .. psi_{n1-1} from the checkpoint
     std::vector<std::unique_ptr<Mps>> states;
