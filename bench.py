@@ -45,6 +45,13 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3}
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
+# HBM bytes of one centre apply from the hardware-counter runs of this workload
+# (profiles/heff_L24_D1024_fp64_counters.md): FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB), the
+# factors a 1 GiB device-to-device copy reads on the same counters.  They hold for the plan
+# they were taken on (task counts and T bytes below) and this GEMM kernel.
+COUNTED_TRAFFIC = {"fp64": {"L": 24, "D": 1024, "tasks": [13322, 516], "T_bytes": 15416401760.0,
+                            "bytes": 92.81e9, "read": 75.96e9, "written": 16.85e9, "mfma_busy": 0.61}}
+
 
 def theta_masks(L, c, blocks, S, Tset):
     """Spin-orbital mask of every element of the centre two-site tensor."""
@@ -322,6 +329,11 @@ def main():
             krylov["tflops_by_phase"] = {"heff_executed": tf(cnt[1], cnt[2]), "env_executed": tf(cnt[7], cnt[3]),
                                          "premix_executed": tf(cnt[8], cnt[5])}
 
+    ct = COUNTED_TRAFFIC.get(args.precision)
+    traffic = None
+    if ct and (L, D) == (ct["L"], ct["D"]) and [int(plan_stats[4]), int(plan_stats[5])] == ct["tasks"] \
+            and plan_stats[3] == ct["T_bytes"]:
+        traffic = ct["bytes"]
     line = {
         "metric": "H_eff*theta TFLOP/s + Krylov steps/s @L=24 D=1024, mixed vs FP64",
         "value": value,
@@ -341,7 +353,10 @@ def main():
                                f"{len(blocks)} blocks",
                    "precision": args.precision, "algorithmic_flops_per_step": flops},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[args.precision], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK[args.precision], "traffic": None,
+                     "frac": achieved / PEAK[args.precision], "traffic": traffic,
+                     "traffic_source": None if traffic is None else
+                     "rocprofv3 FETCH_SIZE / WRITE_SIZE of this plan, scaled by a 1 GiB copy "
+                     "(profiles/heff_L24_D1024_fp64_counters.md); HBM bytes per apply",
                      "kernel": "the grouped block-GEMM launches of one H_eff*theta, replayed as one HIP graph "
                                f"(event-timed on the library stream, {ms_kernel:.2f} ms per step)"},
         "cpu_baseline": cpu,
