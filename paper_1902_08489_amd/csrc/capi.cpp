@@ -754,9 +754,7 @@ extern "C" tdmps_status tdmps_pulse_forward(tdmps_mpo H0, const double* h0, cons
     r.prm = *prm;
     r.h0.assign(h0, h0 + L * L);
     r.m.assign(m, m + L * L);
-    r.Ht = H0->host;
-    r.Hm = H0->host;
-    r.Ht1 = H0->host;
+    for (auto& f : r.field) f = H0->host;
     r.M = build_mpo(L, m, nullptr, 0.0, false);
     r.mu = mu->host;
     Contractor C = make_contractor(psi0->ctx, prm);

@@ -69,7 +69,9 @@ extern "C" tdmps_status tdmps_mpo_one_body(tdmps_ctx ctx, int32_t L, const doubl
 extern "C" tdmps_status tdmps_mpo_set_one_body(tdmps_mpo mpo, const double* h) {
   return guard([&] {
     TDMPS_REQUIRE(mpo && h, TDMPS_ERR_ARG, "NULL argument");
+    const uint64_t old = mpo->host.version;
     mpo_set_one_body(mpo->host, h);
+    premix_cache_forget(old);  // no handle holds the old version any more
   });
 }
 

@@ -194,6 +194,18 @@ double premix_structures_built() {
   return (double)g_skel_built;
 }
 
+void premix_cache_forget(uint64_t version) {
+  std::lock_guard<std::mutex> lk(g_skel_mu);
+  for (auto it = g_skel.begin(); it != g_skel.end();) {
+    if (it->first.version == version) {
+      g_skel_bytes -= it->second.bytes;
+      it = g_skel.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
 namespace {
 
 // With ext != nullptr the premix products are appended to *ext (run by the caller) instead

@@ -327,6 +327,9 @@ SideOps premix_right(Contractor& C, const Env& R, const MpoHost& W, int site);
 
 // Premix structures built so far in the process (misses of the per-operator cache).
 double premix_structures_built();
+// Drops the cached premix structures of an operator version that no operator holds any more
+// (its one-body part was rewritten): they could never be hit again.
+void premix_cache_forget(uint64_t version);
 Env env_left_update(Contractor& C, const SideOps& ops, const Mps* bra, const cplx* bra_site, const SiteLayout& bl,
                     const Bond& bra_l, const Bond& bra_r, const cplx* ket_site, const SiteLayout& kl,
                     const Bond& ket_l, const Bond& ket_r, const MpoHost& W);

@@ -36,16 +36,36 @@ void set_field(PulseRun& r, MpoHost& H, double t) {
   const double e = r.amplitude * shape(r, t);
   std::vector<double> h(r.h0.size());
   for (size_t i = 0; i < h.size(); ++i) h[i] = r.h0[i] + e * r.m[i];
+  const uint64_t old = H.version;
   mpo_set_one_body(H, h.data());
+  bool shared = false;  // the pool starts with copies of H0, all of H0's version
+  for (const auto& f : r.field) shared |= &f != &H && f.version == old;
+  if (!shared) premix_cache_forget(old);
+}
+
+// H at time half * dt / 2 (the RK4 stage times are whole and half steps), from the pool
+const MpoHost* field_at(PulseRun& r, int64_t half) {
+  int slot = -1;
+  for (int i = 0; i < PulseRun::NFIELD; ++i)
+    if (r.field_key[i] == half) slot = i;
+  if (slot < 0) {
+    slot = 0;
+    for (int i = 1; i < PulseRun::NFIELD; ++i)
+      if (r.field_used[i] < r.field_used[slot]) slot = i;
+    set_field(r, r.field[slot], half * r.dt / 2);
+    r.field_key[slot] = half;
+  }
+  r.field_used[slot] = ++r.field_clock;
+  return &r.field[slot];
 }
 
 Mps* step(Contractor& C, PulseRun& r, const Mps* psi, int n) {
-  const double t = n * r.dt;
-  set_field(r, r.Ht, t);
-  set_field(r, r.Hm, t + r.dt / 2);
-  set_field(r, r.Ht1, t + r.dt);
+  // three lookups in a pool of four: none of them evicts another of this step
+  const MpoHost* Ht = field_at(r, 2 * (int64_t)n);
+  const MpoHost* Hm = field_at(r, 2 * (int64_t)n + 1);
+  const MpoHost* Ht1 = field_at(r, 2 * (int64_t)n + 2);
   FitOut fo;
-  return rk4_step(C, &r.Ht, &r.Hm, &r.Ht1, psi, r.dt, r.prm, &fo);
+  return rk4_step(C, Ht, Hm, Ht1, psi, r.dt, r.prm, &fo);
 }
 
 Mps* combine(Contractor& C, const std::vector<FitTerm>& terms, const tdmps_fit_params& prm) {
@@ -96,36 +116,38 @@ double pulse_backward(Contractor& C, PulseRun& r) {
     for (int n = n1 - 1; n >= n0; --n) {
       const Mps* psi = states[n - n0].get();
       const double t = n * dt;
-      set_field(r, r.Ht, t);
-      set_field(r, r.Hm, t + dt / 2);
-      set_field(r, r.Ht1, t + dt);
+      const MpoHost* Ht = field_at(r, 2 * (int64_t)n);
+      const MpoHost* Hm = field_at(r, 2 * (int64_t)n + 1);
+      const MpoHost* Ht1 = field_at(r, 2 * (int64_t)n + 2);
       // forward stages
-      std::unique_ptr<Mps> k1(fit(C, &r.Ht, fwd, psi, {}, r.prm, nullptr));
+      std::unique_ptr<Mps> k1(fit(C, Ht, fwd, psi, {}, r.prm, nullptr));
       std::unique_ptr<Mps> u2(combine(C, {{cplx{1, 0}, psi}, {cplx{0.5, 0}, k1.get()}}, r.prm));
       k1.reset();
-      std::unique_ptr<Mps> k2(fit(C, &r.Hm, fwd, u2.get(), {}, r.prm, nullptr));
+      std::unique_ptr<Mps> k2(fit(C, Hm, fwd, u2.get(), {}, r.prm, nullptr));
       std::unique_ptr<Mps> u3(combine(C, {{cplx{1, 0}, psi}, {cplx{0.5, 0}, k2.get()}}, r.prm));
       k2.reset();
-      std::unique_ptr<Mps> k3(fit(C, &r.Hm, fwd, u3.get(), {}, r.prm, nullptr));
+      std::unique_ptr<Mps> k3(fit(C, Hm, fwd, u3.get(), {}, r.prm, nullptr));
       std::unique_ptr<Mps> u4(combine(C, {{cplx{1, 0}, psi}, {cplx{1, 0}, k3.get()}}, r.prm));
       k3.reset();
       // stage adjoints
       std::unique_ptr<Mps> kb4(mps_clone(lam.get()));
       scale_mps(C.ctx, kb4.get(), cplx{1.0 / 6, 0});
-      std::unique_ptr<Mps> ub4(fit(C, &r.Ht1, adj, kb4.get(), {}, r.prm, nullptr));
+      std::unique_ptr<Mps> ub4(fit(C, Ht1, adj, kb4.get(), {}, r.prm, nullptr));
       std::unique_ptr<Mps> kb3(combine(C, {{cplx{1.0 / 3, 0}, lam.get()}, {cplx{1, 0}, ub4.get()}}, r.prm));
-      std::unique_ptr<Mps> ub3(fit(C, &r.Hm, adj, kb3.get(), {}, r.prm, nullptr));
+      std::unique_ptr<Mps> ub3(fit(C, Hm, adj, kb3.get(), {}, r.prm, nullptr));
       std::unique_ptr<Mps> kb2(combine(C, {{cplx{1.0 / 3, 0}, lam.get()}, {cplx{0.5, 0}, ub3.get()}}, r.prm));
-      std::unique_ptr<Mps> ub2(fit(C, &r.Hm, adj, kb2.get(), {}, r.prm, nullptr));
+      std::unique_ptr<Mps> ub2(fit(C, Hm, adj, kb2.get(), {}, r.prm, nullptr));
       std::unique_ptr<Mps> kb1(combine(C, {{cplx{1.0 / 6, 0}, lam.get()}, {cplx{0.5, 0}, ub2.get()}}, r.prm));
       // gradient of this step: 2 dt sum_s f(t_s) Im <kb_s|M|u_s>
-      const double fs[4] = {shape(r, t), shape(r, t + dt / 2), shape(r, t + dt / 2), shape(r, t + dt)};
+      // the stage times of the operators above (half-step indices 2n, 2n + 1, 2n + 1, 2n + 2)
+      const double th = (2 * (int64_t)n + 1) * dt / 2, t1 = (2 * (int64_t)n + 2) * dt / 2;
+      const double fs[4] = {shape(r, t), shape(r, th), shape(r, th), shape(r, t1)};
       const Mps* kb[4] = {kb1.get(), kb2.get(), kb3.get(), kb4.get()};
       const Mps* us[4] = {psi, u2.get(), u3.get(), u4.get()};
       for (int s = 0; s < 4; ++s)
         if (fs[s] != 0.0) grad += 2 * dt * fs[s] * sandwich(C, r.M, kb[s], us[s]).y;
       // lam_n = lam + ub2 + ub3 + ub4 + A_1^H kb1
-      std::unique_ptr<Mps> a1(fit(C, &r.Ht, adj, kb1.get(), {}, r.prm, nullptr));
+      std::unique_ptr<Mps> a1(fit(C, Ht, adj, kb1.get(), {}, r.prm, nullptr));
       lam.reset(combine(C,
                         {{cplx{1, 0}, lam.get()},
                          {cplx{1, 0}, ub2.get()},

@@ -15,7 +15,14 @@ struct PulseRun {
   int nsteps = 0, every = 1;  // RK4 steps, checkpoint interval
   tdmps_fit_params prm{};
   std::vector<double> h0, m;  // one-body integrals of H0 and of the coupling M (L x L)
-  MpoHost Ht, Hm, Ht1;        // H at the stage times (one-body part rewritten per step)
+  // H at the stage times, one operator per half-step index (time = index * dt / 2): a pool of
+  // four whose least recently used member is rewritten, so that H(t + dt) of one step is H(t)
+  // of the next (and of the previous one in the adjoint pass) without a new operator version
+  static constexpr int NFIELD = 4;
+  MpoHost field[NFIELD];
+  int64_t field_key[NFIELD] = {-1, -1, -1, -1};
+  uint64_t field_used[NFIELD] = {0, 0, 0, 0};
+  uint64_t field_clock = 0;
   MpoHost M, mu;              // coupling operator and observable
   std::vector<std::unique_ptr<Mps>> ckpt;  // psi_0, psi_every, ...
   std::unique_ptr<Mps> last;               // psi_N

@@ -1,6 +1,7 @@
 // Block-sparse layouts, device buffers, task plans and basic state constructors.
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -304,8 +305,15 @@ void GemmPlan::finalize(Ctx* ctx, int precision) {
   // real-A products (premix) take the cost model over the shapes whose real-A kernels keep
   // every value in registers (128 x 48 and 96 x 64 spill there)
   auto usable = [&](int c) { return !real_a || (gemm_tile_m(c) * gemm_tile_n(c) < 6144); };
+  static const int longk_cfg = std::getenv("TDMPS_TILE_LONGK") ? std::atoi(std::getenv("TDMPS_TILE_LONGK")) : -1;
+  static const double lam = std::getenv("TDMPS_TILE_LAMBDA") ? std::atof(std::getenv("TDMPS_TILE_LAMBDA")) : 0.0;
   auto pick = [&](const GemmTask& t) {
     if (ctx->tile_cfg >= 0 && usable(ctx->tile_cfg)) return ctx->tile_cfg;
+    if (longk_cfg >= 0) {
+      int64_t k = 0;
+      for (int s = t.seg0; s < t.seg0 + t.nseg; ++s) k += (int64_t)nsegs[s].nred * nsegs[s].k;
+      if (k >= 512) return longk_cfg;
+    }
     if (tt_tab && !real_a) {
       int64_t k = 0;
       for (int s = t.seg0; s < t.seg0 + t.nseg; ++s) k += (int64_t)nsegs[s].nred * nsegs[s].k;
@@ -317,7 +325,7 @@ void GemmPlan::finalize(Ctx* ctx, int precision) {
       if (!usable(c)) continue;
       const int bm = gemm_tile_m(c), bn = gemm_tile_n(c);
       const double tiles = (double)((t.m + bm - 1) / bm) * ((t.n + bn - 1) / bn);
-      const double cost = tiles * bm * bn / eff[c];
+      const double cost = std::max(tiles * bm * bn / eff[c], lam * tiles * (bm + bn));
       if (cost < bc) {
         bc = cost;
         best = c;
