@@ -40,10 +40,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Dense MFMA peaks (TFLOP/s) in algorithmic flops: the BF16 split runs three bf16 products
-# per real product, so its algorithmic peak is the bf16 rate (2500) over three.
-PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3}
-PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+# Dense MFMA peaks (TFLOP/s) in algorithmic flops: the BF16 splits run three (hi + lo) or six
+# (hi + mid + lo) bf16 products per real product, so their algorithmic peaks are the bf16 rate
+# (2500) over three and over six.
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3, "bf16x6": 2500.0 / 6}
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 
 # HBM bytes of one centre apply from the hardware-counter runs of this workload
 # (profiles/heff_L24_D1024_fp64_counters.md): FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB), the
@@ -137,7 +138,7 @@ def main():
     ap.add_argument("--init", default="random", choices=["random", "det"],
                     help="Krylov workloads: random block state at full D, or the ionised determinant")
     ap.add_argument("--observe", type=int, default=0, help="Krylov workloads: record norm, energy, dipole every step")
-    ap.add_argument("--precisions", default="fp64,fp32,bf16x3",
+    ap.add_argument("--precisions", default="fp64,fp32,bf16x3,bf16x6",
                     help="precision workload: the precisions to run (FP64 is the reference)")
     ap.add_argument("--reference", default=None,
                     help="precision workload without fp64: JSON line of an FP64 run of the same workload")
@@ -233,7 +234,7 @@ def main():
     mixed = None
     if args.mixed and args.precision == "fp64":
         mixed = {}
-        for pname in ("fp32", "bf16x3"):
+        for pname in ("fp32", "bf16x3", "bf16x6"):
             op.set_precision(PREC[pname])
             if args.tune:
                 ctx.autotune(PREC[pname])
@@ -345,8 +346,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "c128 (f64 MFMA)", "fp32": "c64 (f32 MFMA)", "bf16x3": "bf16 split, f32 accumulate"}[
-            args.precision],
+        "dtype": {"fp64": "c128 (f64 MFMA)", "fp32": "c64 (f32 MFMA)", "bf16x3": "bf16 split, f32 accumulate",
+                  "bf16x6": "bf16 three-term split, f32 accumulate"}[args.precision],
         "data": "synthetic (seeded integrals and determinant-basis state)",
         "config": {"workload": f"centre two-site H_eff*theta, L={L} N={Nu + Nd} D={D} sigma=1.0, "
                                f"MPO bond dim {int(mpo.bond_dims()[L // 2])}, theta {tot // 2} complex elements in "
@@ -501,7 +502,7 @@ def other_workload(args, progress):
             trajs = {}
             precs = [p for p in args.precisions.split(",") if p]
             if not precs or any(p not in PREC for p in precs):
-                raise SystemExit("--precisions: a comma-separated list of fp64, fp32, bf16x3")
+                raise SystemExit("--precisions: a comma-separated list of fp64, fp32, bf16x3, bf16x6")
             ref_src = "this run"
             if "fp64" not in precs:
                 # FP64 reference trajectory of an earlier run of the same workload

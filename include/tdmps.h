@@ -58,7 +58,11 @@ enum {
   TDMPS_ERR_UNSUPPORTED = -7  /* feature not available in this build                    */
 };
 
-enum { TDMPS_FP64 = 0, TDMPS_FP32 = 1, TDMPS_BF16X3 = 2 };
+/* Contraction precisions: FP64; FP32 products; BF16 split x = hi + lo (16 significant bits
+ * per operand, three bf16 products per real product); BF16 three-term split x = hi + mid + lo
+ * (all 24 bits of the FP32 value, six bf16 products: FP32 accuracy on the bf16 matrix units).
+ * All accumulate in FP32 (the reduced ones) and keep SVD / Krylov algebra in FP64. */
+enum { TDMPS_FP64 = 0, TDMPS_FP32 = 1, TDMPS_BF16X3 = 2, TDMPS_BF16X6 = 3 };
 enum { TDMPS_KRYLOV_ORTHO = 0, TDMPS_KRYLOV_NONORTHO = 1 };
 
 /* Parameters of the variational fit (Methods, Eq. (add_min)).
@@ -68,7 +72,11 @@ enum { TDMPS_KRYLOV_ORTHO = 0, TDMPS_KRYLOV_NONORTHO = 1 };
  *  conv_tol   : stop when the relative change of |C|^2 between sweeps is below this
  *               (0 = always run n_sweeps).
  *  svd_cutoff : singular values <= svd_cutoff * sigma_max are dropped (at least one kept).
- *  precision  : TDMPS_FP64 / TDMPS_FP32 / TDMPS_BF16X3 for the block contractions.
+ *  precision  : TDMPS_FP64 / TDMPS_FP32 / TDMPS_BF16X3 / TDMPS_BF16X6 for the block
+ *               contractions.  In the reduced precisions the H_eff products keep their operands and their
+ *               intermediate in FP32 storage (FP32 copies of the environment operators and of
+ *               theta); a context created with the environment variable TDMPS_MIXED_STORAGE=0
+ *               keeps FP64 storage.  SVD, QR and the Krylov algebra are FP64 in every mode.
  *  batched    : 1 = one grouped launch per contraction stage (default); 0 = one launch
  *               per block product (reference form used for comparisons). */
 typedef struct {
@@ -307,7 +315,7 @@ tdmps_status tdmps_heff_apply(tdmps_heff op, const void* theta_in_dev, void* the
  * streams) race and must not be issued.  Returns after the context stream has finished. */
 #define TDMPS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 tdmps_status tdmps_heff_apply_noalloc(tdmps_heff op, const void* theta_in_dev, void* theta_out_dev);
-/* Contraction precision of later applies (TDMPS_FP64, TDMPS_FP32, TDMPS_BF16X3); the
+/* Contraction precision of later applies (TDMPS_FP64, TDMPS_FP32, TDMPS_BF16X3, TDMPS_BF16X6); the
  * environments are kept.  TDMPS_ERR_ARG for other values. */
 tdmps_status tdmps_heff_set_precision(tdmps_heff op, int32_t precision);
 /* Algorithmic flops of one apply (8 per complex multiply-add of the block products). */

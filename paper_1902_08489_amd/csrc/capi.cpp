@@ -78,7 +78,7 @@ void check_prm(const tdmps_fit_params* p) {
   TDMPS_REQUIRE(p, TDMPS_ERR_ARG, "NULL fit parameters");
   TDMPS_REQUIRE(p->Dmax >= 1 && p->n_sweeps >= 1, TDMPS_ERR_ARG, "Dmax and n_sweeps must be >= 1");
   TDMPS_REQUIRE(p->svd_cutoff >= 0 && std::isfinite(p->svd_cutoff), TDMPS_ERR_ARG, "bad svd_cutoff");
-  TDMPS_REQUIRE(p->precision == TDMPS_FP64 || p->precision == TDMPS_FP32 || p->precision == TDMPS_BF16X3,
+  TDMPS_REQUIRE(p->precision >= TDMPS_FP64 && p->precision <= TDMPS_BF16X6,
                 TDMPS_ERR_ARG, "unknown precision");
 }
 
@@ -157,7 +157,7 @@ extern "C" tdmps_status tdmps_ctx_set_tile_config(tdmps_ctx ctx, int32_t cfg) {
 extern "C" tdmps_status tdmps_ctx_autotune(tdmps_ctx ctx, int32_t precision, int32_t* cfg_out, double* tflops_out) {
   return guard([&] {
     TDMPS_REQUIRE(ctx, TDMPS_ERR_ARG, "NULL argument");
-    TDMPS_REQUIRE(precision == TDMPS_FP64 || precision == TDMPS_FP32 || precision == TDMPS_BF16X3, TDMPS_ERR_ARG,
+    TDMPS_REQUIRE(precision >= TDMPS_FP64 && precision <= TDMPS_BF16X6, TDMPS_ERR_ARG,
                   "unknown precision");
     dev_bind(ctx->device, ctx->stream);
     TileTable t;
@@ -685,7 +685,7 @@ extern "C" tdmps_status tdmps_heff_apply_noalloc(tdmps_heff h, const void* in, v
 extern "C" tdmps_status tdmps_heff_set_precision(tdmps_heff h, int32_t precision) {
   return guard([&] {
     TDMPS_REQUIRE(h, TDMPS_ERR_ARG, "NULL argument");
-    TDMPS_REQUIRE(precision == TDMPS_FP64 || precision == TDMPS_FP32 || precision == TDMPS_BF16X3, TDMPS_ERR_ARG,
+    TDMPS_REQUIRE(precision >= TDMPS_FP64 && precision <= TDMPS_BF16X6, TDMPS_ERR_ARG,
                   "unknown precision");
     if (precision == h->precision) return;
     dev_bind(h->ctx->device, h->ctx->stream);

@@ -146,7 +146,7 @@ struct tdmps_ctx_s {
   // Tile shape of the grouped GEMM: tile_cfg >= 0 forces one configuration for every task;
   // otherwise a tuned table (tdmps_ctx_autotune) is used where present, else the cost model.
   int tile_cfg = -1;
-  tdmps::TileTable tune[3];
+  tdmps::TileTable tune[4];  // per precision
   int tune_gen = 0;  // bumped whenever the tile choice rules change (plans made before are stale)
   // Work of a context is ordered on one stream, so the host synchronises only where it reads
   // device data.  With phase_sync (environment variable TDMPS_PHASE_TIMING set at context

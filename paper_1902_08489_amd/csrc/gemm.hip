@@ -219,7 +219,10 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 //   P32  : FP32 MFMA 16x16x4, FP32 accumulate (LDS: float2)
 //   PBF3 : bf16 split x = hi + lo of the FP32-rounded operand, products hi*hi + hi*lo + lo*hi
 //          on the 16x16x32 bf16 MFMA with FP32 accumulate (LDS: realified hi / lo planes)
-enum { P64 = 0, P32 = 1, PBF3 = 2 };
+//   PBF6 : three-term split x = hi + mid + lo (all 24 bits of the FP32 value), products
+//          hi*hi + hi*mid + mid*hi + hi*lo + lo*hi + mid*mid (every term down to 2^-16 of the
+//          leading one; the dropped ones are 2^-24 and below), FP32 accumulate
+enum { P64 = 0, P32 = 1, PBF3 = 2, PBF6 = 3 };
 
 
 template <int BM, int BN, int PREC>
@@ -247,10 +250,24 @@ struct Smem<BM, BN, PBF3> {
   __bf16 Ah[BM][40], Al[BM][40];
   __bf16 Bh[2 * BN][40], Bl[2 * BN][40];
 };
+template <int BM, int BN>
+struct Smem<BM, BN, PBF6> {
+  // as PBF3 with a third (mid) plane
+  __bf16 Ah[BM][40], Am[BM][40], Al[BM][40];
+  __bf16 Bh[2 * BN][40], Bm[2 * BN][40], Bl[2 * BN][40];
+};
 
 __device__ __forceinline__ void split_bf16(float f, __bf16& h, __bf16& l) {
   h = (__bf16)f;
   l = (__bf16)(f - (float)h);
+}
+
+// f = h + m + l: each difference is exact in FP32 (it keeps at most 16, then 8, significant bits)
+__device__ __forceinline__ void split3_bf16(float f, __bf16& h, __bf16& m, __bf16& l) {
+  h = (__bf16)f;
+  const float r = f - (float)h;
+  m = (__bf16)r;
+  l = (__bf16)(r - (float)m);
 }
 
 __device__ __forceinline__ double2 scale(double2 v, bool conj, double2 alpha) {
@@ -275,7 +292,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                                                    const int32_t* __restrict__ tile_task, int64_t total_tiles,
                                                    int64_t tile_offset) {
   constexpr int BK = PREC == P64 ? 8 : 16;  // complex k per LDS stage (FP64: fewer live registers)
-  constexpr int BMAP = PREC == PBF3 ? BMAP_K : BMAP_N;
+  constexpr bool BF = PREC == PBF3 || PREC == PBF6;
+  constexpr int BMAP = BF ? BMAP_K : BMAP_N;
   static_assert(!(S32 && PREC == P64), "FP64 products read FP64 operands");
   static_assert(!RA || (PREC == P64 && !S32), "real-A products are FP64");
   typedef typename std::conditional<S32, float2, double2>::type E;
@@ -357,6 +375,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
           *(double2*)&sm.A[rr][2 * kk] = v;
         } else if constexpr (PREC == P32) {
           *(float2*)&sm.A[rr][2 * kk] = make_float2((float)v.x, (float)v.y);
+        } else if constexpr (PREC == PBF6) {
+          __bf16 xh, xm, xl, yh, ym, yl;
+          split3_bf16(v.x, xh, xm, xl);
+          split3_bf16(v.y, yh, ym, yl);
+          *(uint32_t*)&sm.Ah[rr][2 * kk] = pack_bf16(xh, yh);
+          *(uint32_t*)&sm.Am[rr][2 * kk] = pack_bf16(xm, ym);
+          *(uint32_t*)&sm.Al[rr][2 * kk] = pack_bf16(xl, yl);
         } else {
           __bf16 xh, xl, yh, yl;
           split_bf16(v.x, xh, xl);
@@ -386,6 +411,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
           const float re = (float)v.x, im = (float)v.y;
           *(float2*)&sm.B[2 * kk][2 * cc] = make_float2(re, im);
           *(float2*)&sm.B[2 * kk + 1][2 * cc] = make_float2(-im, re);
+        } else if constexpr (PREC == PBF6) {
+          // the split of -Im is the negated split of Im (bf16 negation is exact)
+          __bf16 rh, rm, rl, ih, im, il;
+          split3_bf16(v.x, rh, rm, rl);
+          split3_bf16(v.y, ih, im, il);
+          *(uint32_t*)&sm.Bh[2 * cc][2 * kk] = pack_bf16(rh, -ih);
+          *(uint32_t*)&sm.Bm[2 * cc][2 * kk] = pack_bf16(rm, -im);
+          *(uint32_t*)&sm.Bl[2 * cc][2 * kk] = pack_bf16(rl, -il);
+          *(uint32_t*)&sm.Bh[2 * cc + 1][2 * kk] = pack_bf16(ih, rh);
+          *(uint32_t*)&sm.Bm[2 * cc + 1][2 * kk] = pack_bf16(im, rm);
+          *(uint32_t*)&sm.Bl[2 * cc + 1][2 * kk] = pack_bf16(il, rl);
         } else {
           // B' = [[Re, Im], [-Im, Re]] per complex element, stored transposed (column-major)
           __bf16 rh, rl, ih, il, nh, nl;
@@ -403,7 +439,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     Cursor<E> nx = cur;
     const bool more = nx.advance(bidx, KSTEP);
     if (more) st.load(nx, T, m0, n0, tid);
-    if constexpr (PREC == PBF3) {
+    if constexpr (PREC == PBF6) {
+      bf8 ah[TM], am[TM], al[TM];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        ah[i] = *(const bf8*)&sm.Ah[wm + i * 16 + l16][8 * lq];
+        am[i] = *(const bf8*)&sm.Am[wm + i * 16 + l16][8 * lq];
+        al[i] = *(const bf8*)&sm.Al[wm + i * 16 + l16][8 * lq];
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int rc = 2 * wn + j * 16 + l16;
+        const bf8 bh = *(const bf8*)&sm.Bh[rc][8 * lq];
+        const bf8 bm = *(const bf8*)&sm.Bm[rc][8 * lq];
+        const bf8 bl = *(const bf8*)&sm.Bl[rc][8 * lq];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          // smallest terms first
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[i], bm, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bm, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[i], bh, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+        }
+      }
+    } else if constexpr (PREC == PBF3) {
       bf8 ah[TM], al[TM];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
@@ -563,8 +624,8 @@ void launch_cfg(const GemmTask* tasks, const GemmSeg* segs, const int32_t* tile_
                 hipStream_t stream, int64_t off, bool ops32, bool real_a) {
   const int64_t grid = 8 * ((total_tiles + 7) / 8);
   TDMPS_REQUIRE(grid < ((int64_t)1 << 31), TDMPS_ERR_ARG, "too many GEMM tiles in one launch");
-  TDMPS_REQUIRE(!ops32 || precision == TDMPS_FP32 || precision == TDMPS_BF16X3, TDMPS_ERR_ARG,
-                "FP32 operand storage needs the FP32 or BF16-split precision");
+  TDMPS_REQUIRE(!ops32 || precision == TDMPS_FP32 || precision == TDMPS_BF16X3 || precision == TDMPS_BF16X6,
+                TDMPS_ERR_ARG, "FP32 operand storage needs the FP32 or a BF16-split precision");
   TDMPS_REQUIRE(!real_a || (precision == TDMPS_FP64 && !ops32), TDMPS_ERR_ARG, "real-A products are FP64");
   dim3 g((unsigned)grid), block(256);
   if (real_a)
@@ -578,6 +639,10 @@ void launch_cfg(const GemmTask* tasks, const GemmSeg* segs, const int32_t* tile_
     hipLaunchKernelGGL((gemm_kernel<BM, BN, PBF3, true, false>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
   else if (precision == TDMPS_BF16X3)
     hipLaunchKernelGGL((gemm_kernel<BM, BN, PBF3, false, false>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
+  else if (precision == TDMPS_BF16X6 && ops32)
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, PBF6, true, false>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
+  else if (precision == TDMPS_BF16X6)
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, PBF6, false, false>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
   else
     hipLaunchKernelGGL((gemm_kernel<BM, BN, P64, false, false>), g, block, 0, stream, tasks, segs, tile_task, total_tiles, off);
 }

@@ -80,7 +80,6 @@ struct CopyTask {
 // Columns are grouped in blocks of SVD_BLOCK; nblk = number of blocks rounded up to an even
 // count (at least 2), pair_base = exclusive prefix of nblk/2 over the matrices of a batch.
 constexpr int SVD_BLOCK = 8;
-constexpr int SVD_BLOCK2 = 16;  // column blocks of the 32-column round (waves = 32 in launch_svd_round)
 struct SvdMat {
   cplx* G;
   cplx* V;

@@ -333,193 +333,6 @@ __global__ __launch_bounds__(64 * WAVES) void svd_block_round_kernel(const SvdMa
   }
 }
 
-// The same round with blocks of 16 columns (SVD_BLOCK2): a workgroup owns a pair of 32 columns,
-// so a sweep has half the rounds.  Gram matrix: the tiles (I, I), (I, J), (J, J) of the 32 x 32
-// Hermitian M, each formed by two waves over alternate 4-row steps (waves 6 and 7 wait);
-// rotations of the round's column pairs by wave 0 with four lanes per pair (16 disjoint pairs
-// at a time: the 256 cross pairs p in I, q in J in 16 rounds, or in the diagonal round the pairs
-// inside I and inside J in 15 rounds of the circle schedule on 16 columns); P <- P Q and V <- V Q
-// on MFMA, every 16-row tile giving two 16-column output tiles from the 32 input columns.
-constexpr int SVD_PW2 = 2 * SVD_BLOCK2;
-constexpr int SVD_GB2 = 8;
-
-__global__ __launch_bounds__(512) void svd_block32_round_kernel(const SvdMat* __restrict__ mats, int nmats, int round,
-                                                                double tol, int32_t* __restrict__ counter,
-                                                                const int32_t* __restrict__ prev) {
-  static_assert(SVD_BLOCK2 == 16, "16 x 16 MFMA tiles per block");
-  typedef double v4d __attribute__((ext_vector_type(4)));
-  __shared__ double2 Mp[2][3][16][17];  // Gram partials: row half x tile (II, IJ, JJ)
-  __shared__ double2 Ms[SVD_PW2][SVD_PW2 + 1];
-  __shared__ double2 Qs[SVD_PW2][SVD_PW2 + 1];
-  __shared__ int col[SVD_PW2];
-  __shared__ int rotated;
-  if (prev != nullptr && *prev == 0) return;  // converged in an earlier sweep (uniform)
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int l16 = lane & 15, lq = lane >> 4;
-  const int j = find_mat(mats, nmats, blockIdx.x);
-  const SvdMat m = mats[j];
-  const int i = (int)(blockIdx.x - m.pair_base);
-  const bool diag = round < 0;
-  if (round >= m.nblk - 1 || i >= m.nblk / 2) return;  // uniform over the workgroup
-  int bI = 2 * i, bJ = 2 * i + 1;
-  if (!diag) circle_pair(m.nblk, round, i, bI, bJ);
-  if (t < SVD_PW2) {
-    const int c = (t < SVD_BLOCK2 ? bI : bJ) * SVD_BLOCK2 + (t % SVD_BLOCK2);
-    col[t] = c < m.k ? c : -1;
-  }
-  if (t == 0) rotated = 0;
-  __syncthreads();
-
-  // Gram tiles: wave w < 6 forms tile w % 3 over the 4-row steps w / 3, w / 3 + 2, ...
-  if (wave < 6) {
-    const int tile = wave % 3, half = wave / 3;
-    const double2* G = (const double2*)m.G;
-    const int ca = col[(tile == 2 ? SVD_BLOCK2 : 0) + l16];  // A side: block I for II and IJ, J for JJ
-    const int cb = col[(tile == 0 ? 0 : SVD_BLOCK2) + l16];  // B side: block I for II, J for IJ and JJ
-    const int nsteps = (m.ell + 3) >> 2;
-    v4d r1 = {0, 0, 0, 0}, r2 = r1, i1 = r1, i2 = r1;
-    for (int s0 = half; s0 < nsteps; s0 += 2 * SVD_GB2) {
-      double2 va[SVD_GB2], vb[SVD_GB2];
-#pragma unroll
-      for (int u = 0; u < SVD_GB2; ++u) {
-        const int row = 4 * (s0 + 2 * u) + lq;
-        const bool in = row < m.ell;
-        va[u] = (ca >= 0 && in) ? G[(int64_t)ca * m.ell + row] : make_double2(0.0, 0.0);
-        vb[u] = (cb >= 0 && in) ? G[(int64_t)cb * m.ell + row] : make_double2(0.0, 0.0);
-      }
-#pragma unroll
-      for (int u = 0; u < SVD_GB2; ++u) {
-        r1 = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u].x, vb[u].x, r1, 0, 0, 0);
-        i1 = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u].x, vb[u].y, i1, 0, 0, 0);
-        r2 = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u].y, vb[u].y, r2, 0, 0, 0);
-        i2 = __builtin_amdgcn_mfma_f64_16x16x4f64(-va[u].y, vb[u].x, i2, 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) Mp[half][tile][lq + 4 * e][l16] = make_double2(r1[e] + r2[e], i1[e] + i2[e]);
-  }
-  __syncthreads();
-  for (int x = t; x < SVD_PW2 * SVD_PW2; x += 512) {
-    const int a = x >> 5, b = x & 31;
-    double sr, si;
-    if (a < 16 && b < 16) {
-      sr = Mp[0][0][a][b].x + Mp[1][0][a][b].x;
-      si = Mp[0][0][a][b].y + Mp[1][0][a][b].y;
-    } else if (a < 16) {
-      sr = Mp[0][1][a][b - 16].x + Mp[1][1][a][b - 16].x;
-      si = Mp[0][1][a][b - 16].y + Mp[1][1][a][b - 16].y;
-    } else if (b >= 16) {
-      sr = Mp[0][2][a - 16][b - 16].x + Mp[1][2][a - 16][b - 16].x;
-      si = Mp[0][2][a - 16][b - 16].y + Mp[1][2][a - 16][b - 16].y;
-    } else {  // (J, I) = (I, J)^H
-      sr = Mp[0][1][b][a - 16].x + Mp[1][1][b][a - 16].x;
-      si = -(Mp[0][1][b][a - 16].y + Mp[1][1][b][a - 16].y);
-    }
-    Ms[a][b] = make_double2(sr, a == b ? 0.0 : si);
-    Qs[a][b] = make_double2(a == b ? 1.0 : 0.0, 0.0);
-  }
-  __syncthreads();
-
-  // rotations by wave 0: lane l serves pair l / 4 and rows / columns l % 4 + 4 v
-  if (wave == 0) {
-    const int pr = lane >> 2, sub = lane & 3;
-    bool any = false;
-    const int nr = diag ? SVD_BLOCK2 - 1 : SVD_BLOCK2;
-    for (int r = 0; r < nr; ++r) {
-      int p, q;
-      if (diag) {
-        circle_pair(SVD_BLOCK2, r, pr & 7, p, q);
-        if (pr >= 8) {
-          p += SVD_BLOCK2;
-          q += SVD_BLOCK2;
-        }
-      } else {
-        p = pr;
-        q = SVD_BLOCK2 + ((pr + r) & (SVD_BLOCK2 - 1));
-      }
-      Rot R;
-      const double2 g = Ms[p][q];
-      const bool rot = make_rot(Ms[p][p].x, Ms[q][q].x, g.x, g.y, tol, m.thr, R);
-      any |= rot;
-      wave_sync();
-      if (rot) {
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          double2(*X)[SVD_PW2 + 1] = u < 8 ? Ms : Qs;
-          const int x = sub + 4 * (u & 7);
-          const double2 a = X[x][p], b = X[x][q];
-          const double br = R.er * b.x - R.ei * b.y, bi = R.er * b.y + R.ei * b.x;  // e^{-i phi} b
-          X[x][p] = make_double2(R.c * a.x - R.s * br, R.c * a.y - R.s * bi);
-          X[x][q] = make_double2(R.s * a.x + R.c * br, R.s * a.y + R.c * bi);
-        }
-      }
-      wave_sync();
-      if (rot) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int y = sub + 4 * u;
-          const double2 a = Ms[p][y], b = Ms[q][y];
-          const double br = R.er * b.x + R.ei * b.y, bi = R.er * b.y - R.ei * b.x;  // e^{+i phi} b
-          Ms[p][y] = make_double2(R.c * a.x - R.s * br, R.c * a.y - R.s * bi);
-          Ms[q][y] = make_double2(R.s * a.x + R.c * br, R.s * a.y + R.c * bi);
-        }
-      }
-      wave_sync();
-    }
-    if (__any(any) && lane == 0) rotated = 1;
-  }
-  __syncthreads();
-  if (!rotated) return;  // uniform: read after the barrier
-  if (t == 0) atomicAdd(counter, 1);
-
-  // P <- P Q and V <- V Q in 16-row tiles (wave w: tiles w, w + 8, ...); output tile o holds
-  // columns 16 o .. 16 o + 15; k-step s reads input column 4 s + l / 16 at row l % 16
-  double qr[2][8], qi[2][8];
-  int cin[8];
-#pragma unroll
-  for (int s2 = 0; s2 < 8; ++s2) {
-    cin[s2] = col[4 * s2 + lq];
-#pragma unroll
-    for (int o = 0; o < 2; ++o) {
-      const double2 qv = Qs[4 * s2 + lq][16 * o + l16];
-      qr[o][s2] = qv.x;
-      qi[o][s2] = qv.y;
-    }
-  }
-  const int cout0 = col[l16], cout1 = col[16 + l16];
-  for (int pass = 0; pass < 2; ++pass) {
-    double2* X = (double2*)(pass == 0 ? m.G : m.V);
-    const int len = pass == 0 ? m.ell : m.k;
-    const int ntiles = (len + 15) >> 4;
-    for (int tile = wave; tile < ntiles; tile += 8) {
-      const int row = 16 * tile + l16;
-      double2 v[8];
-#pragma unroll
-      for (int s2 = 0; s2 < 8; ++s2)
-        v[s2] = (cin[s2] >= 0 && row < len) ? X[(int64_t)cin[s2] * len + row] : make_double2(0.0, 0.0);
-#pragma unroll
-      for (int o = 0; o < 2; ++o) {
-        v4d ar = {0, 0, 0, 0}, ai = ar, br = ar, bi = ar;
-#pragma unroll
-        for (int s2 = 0; s2 < 8; ++s2) {
-          ar = __builtin_amdgcn_mfma_f64_16x16x4f64(v[s2].x, qr[o][s2], ar, 0, 0, 0);
-          ai = __builtin_amdgcn_mfma_f64_16x16x4f64(v[s2].x, qi[o][s2], ai, 0, 0, 0);
-          br = __builtin_amdgcn_mfma_f64_16x16x4f64(v[s2].y, -qi[o][s2], br, 0, 0, 0);
-          bi = __builtin_amdgcn_mfma_f64_16x16x4f64(v[s2].y, qr[o][s2], bi, 0, 0, 0);
-        }
-        const int cout = o == 0 ? cout0 : cout1;
-        if (cout >= 0) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int r = 16 * tile + lq + 4 * e;
-            if (r < len) X[(int64_t)cout * len + r] = make_double2(ar[e] + br[e], ai[e] + bi[e]);
-          }
-        }
-      }
-    }
-  }
-}
-
 // One workgroup row per task; the y dimension strides over the elements of the block.
 __global__ __launch_bounds__(256) void share_kernel(const ShareTask* __restrict__ tasks,
                                                     const double* __restrict__ coef) {
@@ -595,11 +408,8 @@ void launch_svd_init(const SvdMat* mats, int nmats, void* stream) {
 void launch_svd_round(const SvdMat* mats, int nmats, int64_t total_pairs, int round, double tol, int32_t* counter,
                       const int32_t* prev, int waves, void* stream) {
   if (nmats <= 0 || total_pairs <= 0) return;
-  TDMPS_REQUIRE(waves == 4 || waves == 8 || waves == 32, TDMPS_ERR_ARG, "svd round: waves must be 4, 8 or 32");
-  if (waves == 32)  // blocks of SVD_BLOCK2 columns
-    hipLaunchKernelGGL(svd_block32_round_kernel, dim3((unsigned)total_pairs), dim3(512), 0, (hipStream_t)stream, mats,
-                       nmats, round, tol, counter, prev);
-  else if (waves == 4)
+  TDMPS_REQUIRE(waves == 4 || waves == 8, TDMPS_ERR_ARG, "svd round: waves must be 4 or 8");
+  if (waves == 4)
     hipLaunchKernelGGL(svd_block_round_kernel<4>, dim3((unsigned)total_pairs), dim3(64 * 4), 0, (hipStream_t)stream,
                        mats, nmats, round, tol, counter, prev);
   else

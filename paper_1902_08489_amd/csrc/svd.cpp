@@ -93,8 +93,6 @@ struct SvdBatch {
   void run(Ctx* ctx) {
     if (jobs.empty()) return;
     const int nm = (int)jobs.size();
-    static const int blk = std::getenv("TDMPS_SVD_BLOCK") && std::atoi(std::getenv("TDMPS_SVD_BLOCK")) == 16
-                               ? SVD_BLOCK2 : SVD_BLOCK;
     int maxk = 0, maxn = 0;
     std::vector<QrMat> qm(nm);
     std::vector<SvdMat> gmats(nm), xm(nm);
@@ -115,7 +113,7 @@ struct SvdBatch {
       q.cb_base = cblocks;
       cblocks += (J.k + QR_PANEL - 1) / QR_PANEL;
       gmats[j] = SvdMat{q.G, q.V, J.ell, J.k, 2, 0, 0.0};
-      const int nb = (J.n + blk - 1) / blk;
+      const int nb = (J.n + SVD_BLOCK - 1) / SVD_BLOCK;
       SvdMat& x = xm[j];
       x.G = q.X;
       x.V = q.V;
@@ -159,7 +157,7 @@ struct SvdBatch {
     // four waves per block pair while every column is short (256 rows or fewer), eight beyond
     int max_len = 0;
     for (const SvdMat& x : xm) max_len = std::max(max_len, std::max(x.ell, x.k));
-    const int waves = blk == SVD_BLOCK2 ? 32 : max_len <= 256 ? 4 : 8;
+    const int waves = max_len <= 256 ? 4 : 8;
     DevBuf counter(max_sweeps * sizeof(int32_t));
     int32_t* dc = (int32_t*)counter.p;
     dev_zero(counter.p, counter.bytes, ctx->stream);

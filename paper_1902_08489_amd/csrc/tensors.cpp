@@ -300,21 +300,23 @@ void GemmPlan::finalize(Ctx* ctx, int precision) {
   // by the shape's relative throughput (measured on aligned shapes with enough tiles to fill
   // the chip, FP64).
   static const double eff[GEMM_NCFG] = {1.0, 0.92, 0.9, 0.96, 0.82, 0.8, 0.94, 0.85, 0.8, 0.97};
-  const TileTable* tt_tab = (precision >= 0 && precision < 3 && ctx->tune[precision].valid) ? &ctx->tune[precision]
+  const TileTable* tt_tab = (precision >= 0 && precision < 4 && ctx->tune[precision].valid) ? &ctx->tune[precision]
                                                                                            : nullptr;
-  // real-A products (premix) take the cost model over the shapes whose real-A kernels keep
-  // every value in registers (128 x 48 and 96 x 64 spill there)
-  auto usable = [&](int c) { return !real_a || (gemm_tile_m(c) * gemm_tile_n(c) < 6144); };
-  static const int longk_cfg = std::getenv("TDMPS_TILE_LONGK") ? std::atoi(std::getenv("TDMPS_TILE_LONGK")) : -1;
-  static const double lam = std::getenv("TDMPS_TILE_LAMBDA") ? std::atof(std::getenv("TDMPS_TILE_LAMBDA")) : 0.0;
+  // real-A products (premix) and the three-term BF16 split take the cost model over the shapes
+  // whose kernels keep every value in registers (128 x 48 and 96 x 64 spill there)
+  auto usable = [&](int c) {
+    return !(real_a || precision == TDMPS_BF16X6) || (gemm_tile_m(c) * gemm_tile_n(c) < 6144);
+  };
+  // Operand traffic: a tile reads (BM + BN) k operand elements.  The reduced precisions are
+  // bound by staging and operand traffic rather than by the matrix units, so their cost is
+  // the larger of the padded work and lam x the tile's operand reads (lam in padded
+  // multiply-adds per operand element; TDMPS_TILE_LAMBDA overrides); FP64 products hide
+  // the reads behind the matrix work (lam = 0: larger tiles only lose occupancy there).
+  static const char* lam_env = std::getenv("TDMPS_TILE_LAMBDA");
+  const double lam = lam_env ? std::atof(lam_env) : precision == TDMPS_FP64 ? 0.0 : precision == TDMPS_FP32 ? 30.0 : 45.0;
   auto pick = [&](const GemmTask& t) {
     if (ctx->tile_cfg >= 0 && usable(ctx->tile_cfg)) return ctx->tile_cfg;
-    if (longk_cfg >= 0) {
-      int64_t k = 0;
-      for (int s = t.seg0; s < t.seg0 + t.nseg; ++s) k += (int64_t)nsegs[s].nred * nsegs[s].k;
-      if (k >= 512) return longk_cfg;
-    }
-    if (tt_tab && !real_a) {
+    if (tt_tab && !real_a && precision != TDMPS_BF16X6) {
       int64_t k = 0;
       for (int s = t.seg0; s < t.seg0 + t.nseg; ++s) k += (int64_t)nsegs[s].nred * nsegs[s].k;
       return (int)tt_tab->cfg[tile_bucket(t.m)][tile_bucket(t.n)][tile_kbucket(k)];

@@ -15,7 +15,7 @@
 namespace tdmps {
 
 void autotune_tiles(Ctx* ctx, int precision, TileTable& tab) {
-  TDMPS_REQUIRE(precision >= 0 && precision < 3, TDMPS_ERR_ARG, "unknown precision");
+  TDMPS_REQUIRE(precision >= 0 && precision < 4, TDMPS_ERR_ARG, "unknown precision");
   const int KREP[TILE_NK] = {32, 256, 2048};  // representative total reduction per bucket
   const int KCH = 64;                         // reduction split into channels of <= 64 (as in the stacked products)
   const int64_t POOL = int64_t(1) << 23;      // complex elements per operand pool (128 MiB)

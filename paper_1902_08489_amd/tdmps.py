@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_LIB = os.path.join(_HERE, "libtdmps.so")
 
-FP64, FP32, BF16X3 = 0, 1, 2
+FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 KRYLOV_ORTHO, KRYLOV_NONORTHO = 0, 1
 
 STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_SECTOR", -3: "ERR_OOM", -4: "ERR_HIP", -5: "ERR_NUMERIC",
