@@ -236,11 +236,23 @@ def main():
         mixed = {}
         for pname in ("fp32", "bf16x3", "bf16x6"):
             op.set_precision(PREC[pname])
-            if args.tune:
-                ctx.autotune(PREC[pname])
             for _ in range(max(1, args.warmup)):
                 op.apply(tin.data_ptr(), tout.data_ptr())
             pms, pk = timed(probe)
+            rule = "cost model"
+            if args.tune:
+                # the measured tile table of this precision against its cost model; the faster is kept
+                ctx.autotune(PREC[pname])
+                op.apply(tin.data_ptr(), tout.data_ptr())
+                tms, tk = timed(probe)
+                if tms < pms:
+                    pms, pk, rule = tms, tk, "autotuned"
+                else:
+                    ctx.clear_tuning()
+                    if tile_rule == "autotuned":
+                        ctx.autotune(PREC[args.precision])
+                    op.apply(tin.data_ptr(), tout.data_ptr())
+                    pms, pk = timed(probe)
             low = tout.cpu().numpy().view(np.complex128)
             mixed[pname] = {"ms_per_apply": pms, "tflops_algorithmic": flops / (pms * 1e-3) / 1e12,
                             "roofline_frac": flops / (float(np.mean(pk)) * 1e-3) / 1e12 / PEAK[pname],
@@ -248,6 +260,7 @@ def main():
                             "rel_l2_err_vs_fp64": float(np.linalg.norm(low - out) / np.linalg.norm(out)),
                             "speedup_vs_fp64": ms_step / pms,
                             "operand_storage": "fp64" if os.environ.get("TDMPS_MIXED_STORAGE") == "0" else "fp32",
+                            "tile_rule": rule,
                             "T_bytes": ctx.counters()[3]}
             progress(f"{pname}: {pms:.2f} ms per apply")
         op.set_precision(PREC[args.precision])
