@@ -8,7 +8,10 @@ H_eff is the FCI Hamiltonian on 1.06e6 product determinants; theta is seeded com
 Gaussian.  A step is one application of H_eff to theta at the centre bond, inputs resident
 in HBM.  Throughput is algorithmic TFLOP/s (8 flops per complex multiply-add of the block
 products in the order (L theta) -> W -> (. R)), timed with HIP events on the library's
-stream.
+stream.  The line also carries the same apply in the mixed precisions (FP32, BF16 split,
+three-term BF16 split) and one m = 12 Krylov step at the same size in FP64 and in a mixed
+precision (three-term BF16 split by default) from the same random block state, with the
+relative change of norm, energy and dipole.
 
 Other workloads of the benchmark set (each prints its own JSON line; not the default):
   --workload krylov     Krylov time steps (default L = 16, D = 256, m = 10, dt = 0.05), steps/s
@@ -122,6 +125,8 @@ def main():
     ap.add_argument("--krylov", type=int, default=1, help="Krylov steps to time (one sweep per fit)")
     ap.add_argument("--mixed", type=int, default=1, help="also time the FP32 and BF16-split H_eff (FP64 runs only)")
     ap.add_argument("--krylov-m", type=int, default=12, help="Krylov dimension (12 in the benchmark definition)")
+    ap.add_argument("--krylov-mixed", default="bf16x6", choices=["", "fp32", "bf16x3", "bf16x6"],
+                    help="also time the Krylov steps in this precision from the same state ('' skips)")
     ap.add_argument("--check", type=int, default=8, help="sampled outputs checked against Slater-Condon")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-block", type=int, default=1, help="also time one launch per block product (baseline)")
@@ -342,6 +347,29 @@ def main():
             tf = lambda f, t: f / max(t, 1e-9) / 1e12
             krylov["tflops_by_phase"] = {"heff_executed": tf(cnt[1], cnt[2]), "env_executed": tf(cnt[7], cnt[3]),
                                          "premix_executed": tf(cnt[8], cnt[5])}
+        if args.krylov_mixed and args.precision == "fp64":
+            # the same steps from the same state in a mixed precision; norm, energy and dipole of
+            # both results (observable sweeps outside the timed steps)
+            psi64 = psi
+            psi = T.MPS.from_blocks(ctx, bk, dk)
+            prm_mixed = T.fit_params(Dmax=D, n_sweeps=1, precision=PREC[args.krylov_mixed])
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.krylov):
+                psi, _, _ = T.krylov_step(mpo, psi, 0.05, args.krylov_m, True, prm_mixed)
+            torch.cuda.synchronize()
+            dtm = time.perf_counter() - t1
+            progress(f"{args.krylov_mixed} Krylov step: {dtm / args.krylov:.1f} s")
+            mu_op = T.MPO.one_body(ctx, synth.dipole_matrix(L))
+
+            def observables(x):
+                n2 = T.overlap(x, x).real
+                return {"norm2": n2, "energy": T.expect(mpo, x, x).real / n2, "dipole": T.expect(mu_op, x, x).real / n2}
+
+            o64, olow = observables(psi64), observables(psi)
+            krylov["mixed"] = {"precision": args.krylov_mixed, "s_per_step": dtm / args.krylov,
+                               "speedup_vs_fp64": dt / dtm, "observables_fp64": o64,
+                               "rel_err_vs_fp64": {k: abs(olow[k] - o64[k]) / abs(o64[k]) for k in o64}}
 
     ct = COUNTED_TRAFFIC.get(args.precision)
     traffic = None
