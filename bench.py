@@ -312,6 +312,8 @@ def main():
         os.environ["TDMPS_PROGRESS"] = "1"  # the library prints one line per Krylov vector
         bk, dk = synth.random_state(L, Nu, Nd, D, sigma=1.0, seed=L + 5)
         psi = T.MPS.from_blocks(ctx, bk, dk)
+        norm0 = np.sqrt(T.overlap(psi, psi).real)  # the step is linear: scaled to unit norm
+        psi.scale(1.0 / norm0)
         prm = T.fit_params(Dmax=D, n_sweeps=1, precision=PREC[args.precision])
         c0 = ctx.counters()
         built0, alloc0, alloc_s0 = c0[19], c0[17], c0[18]
@@ -352,6 +354,7 @@ def main():
             # both results (observable sweeps outside the timed steps)
             psi64 = psi
             psi = T.MPS.from_blocks(ctx, bk, dk)
+            psi.scale(1.0 / norm0)
             prm_mixed = T.fit_params(Dmax=D, n_sweeps=1, precision=PREC[args.krylov_mixed])
             torch.cuda.synchronize()
             t1 = time.perf_counter()
