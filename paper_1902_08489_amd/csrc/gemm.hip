@@ -326,11 +326,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
   const int l16 = lane & 15, lq = lane >> 4;
   // A wave whose quadrant of the tile lies outside the block (ragged tiles) would only
-  // multiply zero padding: in the mixed precisions it stages operands and takes the barriers
-  // but issues no MFMA (FP32 and the BF16 splits 1.5-3% faster at the L = 24, D = 1024 centre);
-  // the FP64 products measured no gain from the skip, and keep every wave's MFMAs.
-  const bool wlive = PREC == P64 || (__builtin_amdgcn_readfirstlane(wm) < T.m - m0 &&
-                                     __builtin_amdgcn_readfirstlane(wn) < T.n - n0);
+  // multiply zero padding: it stages operands and takes the barriers but issues no MFMA.  The
+  // FP64 32x48 shape (long final-stage reductions) keeps every wave's MFMAs and every k step
+  // (below): the H_eff apply at L = 24, D = 1024 measured faster that way.
+  constexpr bool FULL = PREC == P64 && BM == 32 && BN == 48;
+  const bool wlive = FULL || (__builtin_amdgcn_readfirstlane(wm) < T.m - m0 &&
+                              __builtin_amdgcn_readfirstlane(wn) < T.n - n0);
 
   acc_t acc[TM][TN];
 #pragma unroll
@@ -492,11 +493,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
       }
     } else {
       // realified k of the stage that hold data: the steps past the end of a segment's
-      // reduction would only add the zero padding
-      const int kval = RA ? 2 * BK : 2 * min(BK, cur.K - cur.k0);
+      // reduction would only add the zero padding.  The test serialises each step's LDS reads
+      // with its MFMAs; for the FP64 32x48 shape (three MFMAs a step) that cost more than the
+      // padding saved, and it issues every step.
+      const int kval = RA || FULL ? 2 * BK : 2 * min(BK, cur.K - cur.k0);
 #pragma unroll
       for (int kr = 0; kr < 2 * BK; kr += 4) {
-        if (kr >= kval) break;
+        if (!FULL && kr >= kval) break;
         const int kreal = kr + lq;
         typedef typename std::conditional<PREC == P64, double, float>::type r_t;
         r_t a[TM], bb[TN];
