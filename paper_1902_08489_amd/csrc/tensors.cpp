@@ -298,8 +298,26 @@ void GemmPlan::finalize(Ctx* ctx, int precision) {
   // Tile shape per task: a forced shape (tdmps_ctx_set_tile_config), else the measured best
   // shape of the task's bucket (tdmps_ctx_autotune), else the least padded MFMA work divided
   // by the shape's relative throughput (measured on aligned shapes with enough tiles to fill
-  // the chip, FP64).
-  static const double eff[GEMM_NCFG] = {1.0, 0.92, 0.9, 0.96, 0.82, 0.8, 0.94, 0.85, 0.8, 0.97};
+  // the chip, FP64; the 64 x 32 entry set on the real task mix instead: 0.97 -> 1.05 took the
+  // FP64 H_eff apply at L = 24, D = 1024 from 39.7 to 37.9 ms and left the other precisions as
+  // they were).  TDMPS_TILE_EFF (comma-separated, one value per shape in tile-configuration
+  // order) overrides the table, for measuring other choices.
+  static const std::vector<double> eff = [] {
+    std::vector<double> e = {1.0, 0.92, 0.9, 0.96, 0.82, 0.8, 0.94, 0.85, 0.8, 1.05};
+    if (const char* env = std::getenv("TDMPS_TILE_EFF")) {
+      std::vector<double> v;
+      for (const char* q = env; *q;) {
+        char* end = nullptr;
+        const double x = std::strtod(q, &end);
+        if (end == q || !(x > 0.0)) break;
+        v.push_back(x);
+        q = *end == ',' ? end + 1 : end;
+        if (*end != ',') break;
+      }
+      if (v.size() == e.size()) e = v;
+    }
+    return e;
+  }();
   const TileTable* tt_tab = (precision >= 0 && precision < 4 && ctx->tune[precision].valid) ? &ctx->tune[precision]
                                                                                            : nullptr;
   // real-A products (premix) and the three-term BF16 split take the cost model over the shapes
