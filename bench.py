@@ -54,7 +54,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 # factors a 1 GiB device-to-device copy reads on the same counters.  They hold for the plan
 # they were taken on (task counts and T bytes below) and this GEMM kernel.
 COUNTED_TRAFFIC = {"fp64": {"L": 24, "D": 1024, "tasks": [13322, 516], "T_bytes": 15416401760.0,
-                            "bytes": 93.01e9, "read": 76.11e9, "written": 16.90e9, "mfma_busy": 0.599}}
+                            "bytes": 93.54e9, "read": 76.57e9, "written": 16.97e9, "mfma_busy": 0.623}}
 
 
 def theta_masks(L, c, blocks, S, Tset):
