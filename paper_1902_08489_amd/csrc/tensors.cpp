@@ -331,7 +331,7 @@ void GemmPlan::finalize(Ctx* ctx, int precision) {
   // multiply-adds per operand element; TDMPS_TILE_LAMBDA overrides); FP64 products hide
   // the reads behind the matrix work (lam = 0: larger tiles only lose occupancy there).
   static const char* lam_env = std::getenv("TDMPS_TILE_LAMBDA");
-  const double lam = lam_env ? std::atof(lam_env) : precision == TDMPS_FP64 ? 0.0 : precision == TDMPS_FP32 ? 30.0 : 45.0;
+  const double lam = lam_env ? std::atof(lam_env) : precision == TDMPS_FP64 ? 0.0 : precision == TDMPS_FP32 ? 70.0 : 45.0;
   auto pick = [&](const GemmTask& t) {
     if (ctx->tile_cfg >= 0 && usable(ctx->tile_cfg)) return ctx->tile_cfg;
     if (tt_tab && !real_a && precision != TDMPS_BF16X6) {
