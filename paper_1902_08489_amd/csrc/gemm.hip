@@ -447,6 +447,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     const bool more = nx.advance(bidx, KSTEP);
     if (more) st.load(nx, T, m0, n0, tid);
     if (!wlive) {
+      // the wave's quadrant holds only padding: no MFMA
     } else if constexpr (PREC == PBF6) {
       bf8 ah[TM], am[TM], al[TM];
 #pragma unroll
